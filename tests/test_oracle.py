@@ -1,0 +1,374 @@
+"""Pins of the FP64 oracle against facts other than itself (CPU only).
+
+Each test checks the oracle against something the paper or the mathematics
+fixes: a brute-force sum, the PDE the Green's function solves, an independent
+quadrature, a textbook dense solve, an invariant, a printed constant, or a
+finite difference.  A dropped term, a wrong sign/factor, a transposed operand
+or a wrong pad/crop in the oracle fails at least one of them.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.integrate
+import scipy.special
+
+import oracle
+import workloads
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+
+
+# ---------------------------------------------------------------- P1 --------
+
+@pytest.mark.parametrize("grid,mshapes", [
+    ((13, 10), [None, (25, 19), (26, 20), (32, 27)]),
+    ((7, 9), [None, (14, 18), (13, 17)]),
+])
+def test_direct_sum_equals_fft_2d(grid, mshapes):
+    """Brute-force sum_j W(i-j) f_j equals the zero-padded FFT evaluation for
+    every admissible padded size (pins padding, crop, index wrap, scaling)."""
+    k0 = 2 * np.pi / 6.0 * (1 + 0.03j)
+    dx = 1.0
+    f = workloads.random_field(grid, seed=11)
+    ref = oracle.apply_green_direct(k0, dx, f)
+    for ms in mshapes:
+        G = oracle.GreenOperator(k0, dx, grid, ms)
+        assert rel(G(f), ref) < 1e-13, ms
+
+
+def test_direct_sum_equals_fft_3d():
+    grid = (6, 5, 7)
+    k0 = 2 * np.pi / 5.0 * (1 + 0.02j)
+    dx = 0.7
+    f = workloads.random_field(grid, seed=12)
+    ref = oracle.apply_green_direct(k0, dx, f)
+    for ms in [None, (12, 10, 14), (16, 9, 15)]:
+        G = oracle.GreenOperator(k0, dx, grid, ms)
+        assert rel(G(f), ref) < 1e-13, ms
+
+
+def test_padding_below_linear_size_rejected():
+    with pytest.raises(ValueError):
+        oracle.GreenOperator(1.0, 1.0, (8, 8), (14, 16))
+
+
+# ------------------------------------------------- Green's function (PDE) ---
+
+def _helmholtz_residual(ndim, ppw, extent):
+    lam = 1.0
+    k0 = 2 * np.pi / lam * (1 + 0.02j)
+    dx = lam / ppw
+    n = int(round(extent / dx))
+    grid = (n,) * ndim
+    axes = np.meshgrid(*[np.arange(n) * dx for _ in range(ndim)], indexing="ij")
+    xc = (n // 2) * dx
+    sig = 0.35
+    f = np.exp(-sum((a - xc) ** 2 for a in axes) / sig ** 2).astype(np.complex128)
+    u = oracle.GreenOperator(k0, dx, grid)(f)
+    lap = np.zeros_like(u)
+    for ax in range(ndim):
+        r = lambda s: np.roll(u, s, axis=ax)  # noqa: E731
+        lap += (-r(2) + 16 * r(1) - 30 * u + 16 * r(-1) - r(-2)) / (12 * dx * dx)
+    res = lap + k0 * k0 * u + f
+    inner = tuple(slice(3, n - 3) for _ in range(ndim))
+    return float(np.linalg.norm(res[inner]) / np.linalg.norm(f[inner]))
+
+
+@pytest.mark.parametrize("ndim,ppws,extent", [(2, (16, 32), 3.0), (3, (8, 16), 2.0)])
+def test_green_operator_solves_helmholtz(ndim, ppws, extent):
+    """u = G f satisfies lap u + k0^2 u = -f (Sec. 2.2, Eqs. soln_greens_fn and
+    greens_fn) up to the O(dx^2) cell-quadrature error: the residual is small
+    and falls about 4x when dx halves.  A wrong Green's-function constant,
+    sign, Hankel kind, dx^d factor or self-cell value leaves an O(1) residual."""
+    r1 = _helmholtz_residual(ndim, ppws[0], extent)
+    r2 = _helmholtz_residual(ndim, ppws[1], extent)
+    assert r2 < (3e-3 if ndim == 2 else 1.5e-2), (r1, r2)
+    assert 2.8 < r1 / r2 < 6.0, (r1, r2)
+
+
+@pytest.mark.parametrize("k0", [2 * np.pi / 6 * (1 + 0.004j), 0.9 + 0.2j, 2.5 + 0.0j])
+def test_self_cell_matches_quadrature(k0):
+    """W(0) equals the integral of g over the equal-area disk / equal-volume
+    ball computed by adaptive quadrature."""
+    dx = 1.0
+    a2 = dx / math.sqrt(math.pi)
+    f2 = lambda r, part: part(0.25j * scipy.special.hankel1(0, k0 * r) * 2 * np.pi * r)  # noqa: E731
+    q2 = (scipy.integrate.quad(f2, 0, a2, args=(np.real,), epsabs=0, epsrel=1e-13, limit=200)[0]
+          + 1j * scipy.integrate.quad(f2, 0, a2, args=(np.imag,), epsabs=0, epsrel=1e-13, limit=200)[0])
+    assert abs(oracle.self_cell(k0, dx, 2) - q2) < 1e-12 * abs(q2)
+    a3 = dx * (3 / (4 * math.pi)) ** (1 / 3)
+    f3 = lambda r, part: part(np.exp(1j * k0 * r) / (4 * np.pi * r) * 4 * np.pi * r * r)  # noqa: E731
+    q3 = (scipy.integrate.quad(f3, 0, a3, args=(np.real,), epsabs=0, epsrel=1e-13)[0]
+          + 1j * scipy.integrate.quad(f3, 0, a3, args=(np.imag,), epsabs=0, epsrel=1e-13)[0])
+    assert abs(oracle.self_cell(k0, dx, 3) - q3) < 1e-12 * abs(q3)
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_point_source_gives_green_function(ndim):
+    """A unit point source (density 1/dx^d on one cell) with V = 0 gives
+    u_0(x) = g(k0, |x - x0|) off the source cell."""
+    grid = (11, 9) if ndim == 2 else (7, 6, 5)
+    dx = 0.25
+    k0 = 2 * np.pi * (1 + 0.01j)
+    src = tuple(n // 3 for n in grid)
+    s = np.zeros(grid, dtype=np.complex128)
+    s[src] = 1.0 / dx ** ndim
+    p, res = oracle.solve(k0, dx, s, None, 1, ndim=ndim)
+    idx = np.stack(np.meshgrid(*[np.arange(n) for n in grid], indexing="ij"), axis=-1)
+    r = dx * np.sqrt(np.sum((idx - np.array(src)) ** 2, axis=-1))
+    mask = r > 0
+    if ndim == 2:
+        g = 0.25j * scipy.special.hankel1(0, k0 * r[mask])
+    else:
+        g = np.exp(1j * k0 * r[mask]) / (4 * np.pi * r[mask])
+    assert rel(p[mask], g) < 1e-12
+
+
+# ---------------------------------------------------------------- series ----
+
+def test_zero_potential_gives_first_term_only():
+    """V = 0: every u_n (n >= 1) is exactly zero and p = u_0."""
+    grid = (12, 10)
+    k0 = 1.3 + 0.05j
+    s = workloads.random_field(grid, 3)
+    G = oracle.GreenOperator(k0, 0.5, grid)
+    p, res = oracle.born_series(G, s, np.zeros(grid, np.complex128), 5)
+    assert np.array_equal(p, G(s))
+    assert res[0] == 1.0 and np.all(res[1:] == 0.0)
+
+
+def _small_problem(rho_target, n=12, seed=4):
+    grid = (n, n)
+    dx = 1.0
+    k0 = 2 * np.pi / 6.0 * (1 + 0.01j)
+    V = workloads.random_field(grid, seed) * np.exp(-((np.arange(n)[:, None] - n / 2) ** 2
+                                                      + (np.arange(n)[None, :] - n / 2) ** 2) / 9.0)
+    A = oracle.dense_operator(k0, dx, grid)
+    rho = oracle.spectral_radius(A, V)
+    V = V * (rho_target / rho)
+    s = np.zeros(grid, np.complex128)
+    s[1, 3] = 1.0
+    s[1, 7] = -0.5j
+    return k0, dx, grid, A, V, s
+
+
+def test_series_converges_to_dense_ls_when_radius_below_one():
+    """rho(GV) < 1: partial sums approach the dense Lippmann-Schwinger solution
+    (Sec. 2.2, Eq. TBS_1) geometrically at rate rho (the condition stated under
+    Eq. TBS_2)."""
+    k0, dx, grid, A, V, s = _small_problem(0.5)
+    assert abs(oracle.spectral_radius(A, V) - 0.5) < 1e-10
+    p_inf = oracle.dense_ls(A, V, s)
+    G = oracle.GreenOperator(k0, dx, grid)
+    errs = [rel(oracle.born_series(G, s, V, L)[0], p_inf) for L in (10, 20, 40)]
+    assert errs[2] < 1e-9
+    assert errs[1] < errs[0] * 0.5 ** 10 * 30
+    assert errs[1] > errs[0] * 0.5 ** 10 / 30
+
+
+def test_series_diverges_when_radius_above_one():
+    k0, dx, grid, A, V, s = _small_problem(1.3)
+    G = oracle.GreenOperator(k0, dx, grid)
+    _, res = oracle.born_series(G, s, V, 60)
+    # ||u_n|| / ||p_{n+1}|| tends to a nonzero limit (terms outgrow the sum's
+    # convergence), while for rho < 1 it tends to 0.
+    assert res[-1] > 0.1
+    _, res_ok = oracle.born_series(G, s, V * (0.5 / 1.3), 60)
+    assert res_ok[-1] < 1e-12
+
+
+def test_partial_sum_ls_residual_is_next_term():
+    """p_L - G(V p_L) - G s = -u_L for every L (the recursion under
+    Eq. TBS_1)."""
+    k0, dx, grid, A, V, s = _small_problem(0.7)
+    G = oracle.GreenOperator(k0, dx, grid)
+    for L in (1, 2, 5):
+        pL, _ = oracle.born_series(G, s, V, L)
+        pL1, _ = oracle.born_series(G, s, V, L + 1)
+        uL = pL1 - pL
+        lhs = pL - G(V * pL) - G(s)
+        assert rel(lhs, -uL) < 1e-12
+
+
+def test_dense_operator_matches_fft_operator():
+    k0, dx, grid, A, V, s = _small_problem(0.5, n=9)
+    f = workloads.random_field(grid, 8)
+    assert rel(oracle.GreenOperator(k0, dx, grid)(f), (A @ f.ravel()).reshape(grid)) < 1e-13
+
+
+@pytest.mark.parametrize("L", [1, 3, 8])
+def test_reciprocity(L):
+    """W is even, so every truncated term operator (GV)^n G is complex
+    symmetric: the field at B from a point source at A equals the field at A
+    from B, for any V and L."""
+    grid = (14, 11)
+    dx = 1.0
+    k0 = 2 * np.pi / 5 * (1 + 0.02j)
+    V = 0.05 * workloads.random_field(grid, 21)
+    a, b = (2, 3), (11, 8)
+    s = np.zeros((2,) + grid, np.complex128)
+    s[(0,) + a] = 1.0
+    s[(1,) + b] = 1.0
+    p, _ = oracle.solve(k0, dx, s, V, L)
+    assert abs(p[(0,) + b] - p[(1,) + a]) < 1e-13 * abs(p[(0,) + b])
+
+
+def test_batch_is_linear_and_matches_single():
+    grid = (10, 12)
+    k0 = 1.1 + 0.1j
+    V = 0.2 * workloads.random_field(grid, 5)
+    s = workloads.random_field((3,) + grid, 6)
+    pb, rb = oracle.solve(k0, 0.8, s, V, 6)
+    for b in range(3):
+        p1, r1 = oracle.solve(k0, 0.8, s[b], V, 6)
+        assert rel(pb[b], p1) < 1e-14 and np.allclose(rb[b], r1, rtol=1e-13)
+    pc, _ = oracle.solve(k0, 0.8, 2.0 * s[0] - 1j * s[1], V, 6)
+    assert rel(pc, 2.0 * pb[0] - 1j * pb[1]) < 1e-13
+
+
+def test_residual_definition():
+    grid = (8, 8)
+    k0 = 1.1 + 0.1j
+    V = 0.2 * workloads.random_field(grid, 5)
+    s = workloads.random_field(grid, 6)
+    G = oracle.GreenOperator(k0, 1.0, grid)
+    p3, r3 = oracle.born_series(G, s, V, 3)
+    p2, _ = oracle.born_series(G, s, V, 2)
+    assert r3[0] == pytest.approx(1.0)
+    assert r3[2] == pytest.approx(np.linalg.norm(p3 - p2) / np.linalg.norm(p3), rel=1e-13)
+
+
+# ----------------------------------------------------------- medium model ---
+
+def test_paper_constants():
+    """Scalars the paper prints (golden file with citations)."""
+    g = json.load(open(os.path.join(GOLDEN, "paper_constants.json")))
+    prm = g["params"]
+    f = prm["multiple"] * prm["v_f"] / (prm["n_grid"] * prm["dx"])
+    assert f == pytest.approx(g["frequency_hz"]["value"], rel=g["frequency_hz"]["rtol"])
+    kf = 2 * np.pi * g["frequency_hz"]["value"] / prm["v_f"]
+    assert kf * prm["a"] == pytest.approx(g["kf_a"]["value"], rel=g["kf_a"]["rtol"])
+    nu, a0, v = prm["nu"], prm["alpha0"], prm["v_f"]
+    assert -2 * a0 * v ** (nu - 1) == pytest.approx(g["tau"]["value"], rel=g["tau"]["rtol"])
+    assert 2 * a0 * v ** nu * math.tan(math.pi * nu / 2) == pytest.approx(g["eta"]["value"], rel=g["eta"]["rtol"])
+    assert workloads.alpha0_si(0.75, 1.5) == pytest.approx(g["alpha0_si"]["value"], rel=g["alpha0_si"]["rtol"])
+
+
+def test_wavenumber_solves_paper_dispersion_relation_to_first_order():
+    """K from ``oracle.wavenumber`` makes the plane-wave symbol of the paper's
+    absorbing-dispersive Helmholtz operator (Sec. 2.1.2, Eq.
+    acoustic_waveequn_time_independent_absorbing_dispersion),
+    -K^2 + k_f^2 - i tau omega K^y + eta K^(y+1), vanish to first order in
+    alpha0: the symbol falls as alpha0^2 (a wrong sign or factor in the
+    absorption or dispersion term leaves an O(alpha0) symbol)."""
+    omega, c, y = 2 * np.pi * 5e6, 1540.0, 1.5
+    kf = omega / c
+    sym = []
+    for a0 in (5.5e-10, 5.5e-11):
+        K = complex(oracle.wavenumber(omega, c, a0, y))
+        tau = -2 * a0 * c ** (y - 1)
+        eta = 2 * a0 * c ** y * math.tan(math.pi * y / 2)
+        sym.append(abs(-K * K + kf * kf - 1j * tau * omega * K ** y + eta * K ** (y + 1)))
+    first_order = abs(2 * kf * 5.5e-10 * omega ** y)
+    assert sym[0] < 5e-2 * first_order
+    assert 70 < sym[0] / sym[1] < 130
+
+
+@pytest.mark.parametrize("y", [1.0, 1.5, 1.1])
+def test_wavenumber_absorption_is_power_law(y):
+    """Im k = alpha0 omega^y (Sec. 2.1.2, Eq. power_law_absorption)."""
+    omega, a0 = 2 * np.pi * 3e6, 3e-10
+    k = oracle.wavenumber(omega, np.array([1400.0, 1600.0]), a0, y)
+    assert np.allclose(k.imag, a0 * omega ** y, rtol=1e-14)
+    assert np.allclose(oracle.potential(np.array([1540.0]), omega, 1540.0, a0, y), 0.0, atol=1e-9)
+
+
+# --------------------------------------------------------------- harmonic ---
+
+def test_harmonic_source_from_time_domain():
+    """The second-harmonic source equals the 2 omega Fourier component of the
+    time-domain nonlinear term, moved to the right-hand side in the paper's
+    form lap psi + k^2 psi = -S (Sec. 2.1.4, Eq.
+    acoustic_waveequn_time_dependent_nonlinear: + xi d^2(Psi^2)/dt^2 on the
+    left).  Computed numerically from sampled Psi(t) = Re(p1 e^{-i omega t})."""
+    omega, rho, BA = 2 * np.pi * 3e6, 1000.0, 7.0
+    c = np.array([1500.0, 1540.0, 1600.0])
+    p1 = np.array([1.0 + 2.0j, -0.3 + 0.1j, 2.0 - 1.0j]) * 1e5
+    nt = 64
+    t = np.arange(nt) * (2 * np.pi / omega) / nt
+    Psi = np.real(p1[:, None] * np.exp(-1j * omega * t[None, :]))
+    xi = (1 + BA / 2) / (rho * c ** 4)
+    # xi * d^2(Psi^2)/dt^2 through its exact Fourier series in time
+    spec = np.fft.fft(Psi ** 2, axis=1) / nt
+    # complex amplitude X of the term Re(X e^{-2 i omega t}): component of e^{-2 i omega t}
+    X2 = 2 * spec[:, nt - 2]                       # e^{-2i w t} is fft bin -2
+    term = xi * (-(2 * omega) ** 2) * X2          # d^2/dt^2 -> -(2 omega)^2
+    # lap psi2 + k2^2 psi2 + term = 0  =>  lap psi2 + k2^2 psi2 = -S2 with S2 = term
+    S2 = oracle.harmonic_source(p1, c, omega, rho, BA)
+    assert rel(S2, term) < 1e-12
+
+
+# ---------------------------------------------------------------- adjoint ---
+
+def test_adjoint_green_operator_dot_product():
+    grid = (9, 13)
+    G = oracle.GreenOperator(1.3 + 0.07j, 0.6, grid)
+    f = workloads.random_field(grid, 1)
+    h = workloads.random_field(grid, 2)
+    lhs = np.vdot(h, G(f))
+    rhs = np.vdot(G(h, adjoint=True), f)
+    assert abs(lhs - rhs) < 1e-13 * abs(lhs)
+
+
+def test_adjoint_series_dot_product():
+    """d Re<q, p_L> along a direction dV equals Re sum dV g_V (directional
+    derivative by complex-step-free central difference in FP64)."""
+    grid = (10, 9)
+    k0 = 2 * np.pi / 6 * (1 + 0.02j)
+    G = oracle.GreenOperator(k0, 1.0, grid)
+    V = 0.05 * workloads.random_field(grid, 3)
+    s = workloads.random_field(grid, 4)
+    q = workloads.random_field(grid, 5)
+    dV = workloads.random_field(grid, 6)
+    L = 6
+    g = oracle.adjoint_series_gradient(G, s, V, L, q)
+    h = 1e-6
+    fp = np.vdot(q, oracle.born_series(G, s, V + h * dV, L)[0]).real
+    fm = np.vdot(q, oracle.born_series(G, s, V - h * dV, L)[0]).real
+    fd = (fp - fm) / (2 * h)
+    assert abs(fd - np.sum(dV * g).real) < 1e-7 * abs(fd)
+    assert np.all(oracle.adjoint_series_gradient(G, s, V, 1, q) == 0)
+
+
+def test_misfit_gradient_matches_finite_differences():
+    """dJ/dc from the adjoint series equals central FD (h = 1e-6 c0) at sampled
+    pixels, in FP64, on a small grid."""
+    prob = workloads.adjoint2d(n=24, nfreq=2, nsrc=2, nrec=8, nterms=5)
+    rec = prob.receivers.copy()
+    p_obs = []
+    for f in prob.freqs:
+        om = 2 * np.pi * f
+        k0 = oracle.background_k0(om, workloads.C0, prob.alpha0, prob.y)
+        V = oracle.potential(prob.c_true, om, workloads.C0, prob.alpha0, prob.y)
+        p, _ = oracle.solve(k0, prob.dx, prob.sources, V, prob.nterms)
+        p_obs.append(p[(slice(None),) + tuple(rec.T)])
+    J, grad = oracle.misfit_gradient(prob.c_model, prob.freqs, prob.dx, workloads.C0, prob.alpha0,
+                                     prob.y, prob.sources, rec, p_obs, prob.nterms)
+    assert J > 0
+    h = 1e-6 * workloads.C0
+    for (iy, ix) in [(12, 12), (8, 15), (16, 5)]:
+        cp = prob.c_model.copy(); cp[iy, ix] += h
+        cm = prob.c_model.copy(); cm[iy, ix] -= h
+        Jp, _ = oracle.misfit_gradient(cp, prob.freqs, prob.dx, workloads.C0, prob.alpha0, prob.y,
+                                       prob.sources, rec, p_obs, prob.nterms)
+        Jm, _ = oracle.misfit_gradient(cm, prob.freqs, prob.dx, workloads.C0, prob.alpha0, prob.y,
+                                       prob.sources, rec, p_obs, prob.nterms)
+        fd = (Jp - Jm) / (2 * h)
+        assert abs(fd - grad[iy, ix]) < 1e-6 * np.max(np.abs(grad)), (iy, ix, fd, grad[iy, ix])
