@@ -1,0 +1,199 @@
+/*
+ * tbs.h -- C ABI of the MI355X traditional-Born-series (TBS) Helmholtz solver.
+ *
+ * The library evaluates the Born series of the Lippmann-Schwinger equation
+ *     psi = G V psi + G S                      (paper Sec. 2.2, Eq. TBS_1)
+ * term by term,
+ *     u_0 = G s,  u_n = G (V u_{n-1}),  p = sum_{n<L} u_n
+ *                                   (Sec. 2.2, Eqs. TBS_2, TBS_input, TBS_algorithm)
+ * where G is the free-space Green's-function convolution (Sec. 2.2,
+ * Eqs. soln_greens_fn and greens_fn) evaluated with zero-padded FFTs, and
+ * V(x) = k(x)^2 - k0^2 carries sound speed, absorption and dispersion
+ * (Sec. 2.1.2, Sec. 2.3.3 Eq. TBS_equation_inhomogeneous).
+ *
+ * Conventions (all entry points):
+ *  - Arrays are C order with x fastest: 2D [y][x], 3D [z][y][x]; a batch of B
+ *    right-hand sides is [B][...].  Complex values are interleaved (re, im):
+ *    dtype TBS_C64 = 2 x float (bit-compatible with torch.complex64),
+ *    TBS_C128 = 2 x double (torch.complex128).
+ *  - "dev" pointers are device (HBM) pointers on the plan's device, owned by
+ *    the caller, and must stay valid until the work queued on the plan's
+ *    stream has finished.  "host" pointers are ordinary host memory.
+ *  - Work is queued asynchronously on the plan's HIP stream; an entry point
+ *    blocks only when it returns values to host memory (residual_out,
+ *    exports).
+ *  - Return value: TBS_OK (0) on success; a negative TBS_ERR_* code leaves the
+ *    outputs unspecified; a positive TBS_WARN_* code means the outputs are
+ *    written but suspicious.  tbs_last_error() describes the last failure of a
+ *    plan.  No C++ exception crosses this interface.
+ *  - A plan is not thread-safe; distinct plans are independent.
+ */
+#ifndef TBS_H
+#define TBS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tbs_plan tbs_plan;
+typedef struct {
+  double re, im;
+} tbs_c128;
+
+enum tbs_dtype {
+  TBS_C64 = 0,  /* complex FP32; partial sums Kahan-compensated */
+  TBS_C128 = 1  /* complex FP64; plain summation */
+};
+
+enum tbs_status {
+  TBS_OK = 0,
+  TBS_ERR_INVALID = -1,     /* bad argument (NULL, size, range, dtype) */
+  TBS_ERR_UNSUPPORTED = -2, /* valid request the library has no kernel for */
+  TBS_ERR_OOM = -3,         /* device allocation failed; nothing leaked */
+  TBS_ERR_HIP = -4,         /* a HIP runtime call failed */
+  TBS_ERR_STATE = -5,       /* call out of order (e.g. solve before tabulate) */
+  TBS_WARN_NONFINITE = 1,   /* a residual is NaN/Inf (non-finite input?) */
+  TBS_WARN_DIVERGING = 2    /* residuals grew over 3 consecutive terms */
+};
+
+enum tbs_adjoint_flags {
+  TBS_ADJ_STORE = 0,     /* keep all L-1 forward partial sums in HBM */
+  TBS_ADJ_RECOMPUTE = 1  /* keep ~sqrt(L) checkpoints and recompute segments */
+};
+
+/* Library version (major*10000 + minor*100 + patch). */
+int tbs_version(void);
+
+/* Human-readable name of a status code (static string). */
+const char *tbs_status_string(int status);
+
+/* ---- host-side helpers (no device needed) ------------------------------ */
+
+/* Padded FFT length the library uses for n physical points: the smallest
+ * length with compiled kernels that is >= padding*n - 1 (>= 2n - 1 makes the
+ * circular convolution equal the linear one, Sec. 2.2 Eq. TBS_1).  Even.
+ * TBS_ERR_UNSUPPORTED if no compiled length is large enough. */
+int tbs_padded_length(int64_t n, int padding, int64_t *m_out);
+
+/* Complex wavenumber of a power-law absorbing, dispersive medium,
+ * k = omega/c + alpha0 omega^y (i + tan(pi y/2)), and k = omega/c + i alpha0
+ * omega for y == 1 (first-order solution of the plane-wave relation of
+ * Sec. 2.1.2, Eq. acoustic_waveequn_time_independent_absorbing_dispersion;
+ * alpha0 in Np m^-1 (rad/s)^-y, Eq. power_law_absorption). */
+int tbs_wavenumber(double omega, double c, double alpha0, double y, tbs_c128 *k_out);
+
+/* Background wavenumber k0 with k0^2 = k(c0)^2 + i eps, Im k0 >= 0
+ * (Sec. 2.2, Eq. acoustic_waveequn6; eps = 0 is the default reading). */
+int tbs_background_k0(double omega, double c0, double alpha0, double y, double eps,
+                      tbs_c128 *k0_out);
+
+/* FP64 Hankel functions H0^(1)(z), H1^(1)(z) for Re z > 0, Im z >= 0, as used
+ * by the 2D Green's function (i/4) H0(k0 r).  Exposed for testing. */
+int tbs_hankel01(tbs_c128 z, tbs_c128 *h0_out, tbs_c128 *h1_out);
+
+/* Self-cell weight W(0): the integral of the Green's function over the disk
+ * (ndim 2) or ball (ndim 3) with the area/volume of one cell of side dx. */
+int tbs_self_cell(int ndim, tbs_c128 k0, double dx, tbs_c128 *w0_out);
+
+/* ---- plans ------------------------------------------------------------- */
+
+/* Create a plan for the operator G on an ndim-dimensional grid.
+ *   grid[3]   : N_x, N_y, N_z physical points (grid[2] ignored when ndim=2)
+ *   dx        : cell size [m], > 0
+ *   k0        : complex background wavenumber, Re k0 > 0, Im k0 >= 0
+ *   padding   : >= 2; padded length per axis = tbs_padded_length(N, padding)
+ *   dtype     : TBS_C64 or TBS_C128 (precision of the series)
+ *   batch     : B >= 1 right-hand sides per solve (they share V and G)
+ *   hip_stream: hipStream_t to queue work on (NULL = the null stream)
+ * Allocates the plan's device buffers (twiddles, intermediates, Kahan
+ * compensation).  *out is NULL on failure.  TBS_ERR_OOM leaks nothing. */
+int tbs_plan_create(tbs_plan **out, int ndim, const int64_t grid[3], double dx, tbs_c128 k0,
+                    int padding, int dtype, int batch, void *hip_stream);
+
+/* Padded lengths (M_x, M_y, M_z; M_z = 1 in 2D) and device bytes held. */
+int tbs_plan_info(const tbs_plan *plan, int64_t padded_out[3], int64_t *device_bytes_out);
+
+/* Queue later work on another stream. */
+int tbs_plan_set_stream(tbs_plan *plan, void *hip_stream);
+
+/* Tabulate the Green spectrum in FP64 on the device: W(m) = dx^d g(k0,|m|dx)
+ * on the padded grid (W(0) = tbs_self_cell), forward FFT, scale 1/prod(M),
+ * fold to the [0, M_x/2] x [0, M_y/2] (x [0, M_z/2]) table, round to the plan
+ * dtype.  Must precede tbs_solve/tbs_adjoint.  Blocks until done. */
+int tbs_green_tabulate(tbs_plan *plan);
+
+/* Test seam: replace the spectrum by fftn(W_pad) given on the host as a full
+ * complex128 array [M_z][M_y][M_x] (unnormalised; must be even per axis). */
+int tbs_green_import(tbs_plan *plan, const tbs_c128 *full_host);
+
+/* Copy the folded, normalised table to the host as complex128
+ * [M_x/2+1][M_y/2+1] (2D) or [M_x/2+1][M_y/2+1][M_z/2+1] (3D). */
+int tbs_green_export(const tbs_plan *plan, tbs_c128 *folded_host);
+
+/* Potential V = k(c)^2 - k0^2 (and optionally dV/dc = -2 k omega / c^2) of a
+ * sound-speed map c (dev, float64 [P]) at angular frequency omega, with
+ * k0^2 = k(c0)^2 + i eps.  V_dev / dVdc_dev: dev, plan dtype [P]; either may
+ * be NULL. */
+int tbs_potential(tbs_plan *plan, const double *c_dev, double omega, double c0, double alpha0,
+                  double y, double eps, void *V_dev, void *dVdc_dev);
+
+/* The L-term Born series for the plan's B right-hand sides.
+ *   source      : dev [B][P] plan dtype, the source density s
+ *   potential   : dev [P] plan dtype, V; NULL means V = 0 (then p = u_0)
+ *   nterms      : L >= 1 summed terms, u_0 included
+ *   p_out       : dev [B][P] plan dtype; receives p = sum_{n<L} u_n
+ *   residual_out: host double [B][L] or NULL; receives ||u_n|| / ||sum_{m<=n} u_m||
+ *                 (whole-grid L2 in FP64; Sec. 3.1 Eq. Error).  Non-NULL makes
+ *                 the call synchronous and enables the TBS_WARN_* checks.
+ * p_out must not alias source or potential. */
+int tbs_solve(tbs_plan *plan, const void *source, const void *potential, int nterms,
+              void *p_out, double *residual_out);
+
+/* Second-harmonic source S2 = -(1/2) xi (2 omega)^2 p1^2, xi = (1 + B/2A) /
+ * (rho c^4) with the local sound speed c (Sec. 2.1.4 Eq. nonlinear_waveeqn_shi2,
+ * Sec. 2.3.4 Eq. TBS_solution_shi_2, sum term only).
+ *   p1_dev: dev [B][P] plan dtype (fundamental field); c_dev: dev float64 [P];
+ *   S2_dev: dev [B][P] plan dtype (may alias p1_dev). */
+int tbs_harmonic_source(tbs_plan *plan, const void *p1_dev, const double *c_dev, double omega,
+                        double rho, double BA, void *S2_dev);
+
+/* Gradient of Re<q, p_L> with respect to V for each right-hand side, i.e. the
+ * adjoint of the truncated series:
+ *   g_V = sum_{m=0}^{L-2} conj(w_m) * P_{L-1-m},  w_0 = G^H q,
+ *   w_m = G^H (conj(V) w_{m-1}),  P_K = sum_{j<K} u_j;  G^H has spectrum conj(G^).
+ *   source, potential, nterms: as tbs_solve (potential must not be NULL)
+ *   adj_source : dev [B][P] plan dtype, q (e.g. R^H (R p - p_obs))
+ *   grad_out   : dev [B][P] plan dtype, g_V per right-hand side
+ *   residual_out: host double [B][L] or NULL: the forward residuals
+ *   flags      : TBS_ADJ_STORE or TBS_ADJ_RECOMPUTE
+ * The forward partial sums are recomputed inside the call. */
+int tbs_adjoint(tbs_plan *plan, const void *source, const void *potential, int nterms,
+                const void *adj_source, void *grad_out, double *residual_out, int flags);
+
+/* Receiver misfit.  rec_dev: dev int64 [nrec] flat spatial indices (distinct);
+ * p_obs_dev: dev [B][nrec] plan dtype.  Writes q_dev (dev [B][P], zero except
+ * q[b][rec[r]] = p[b][rec[r]] - p_obs[b][r]) and J_dev (dev double [1],
+ * J = 1/2 sum |p[b][rec[r]] - p_obs[b][r]|^2). */
+int tbs_misfit(tbs_plan *plan, const void *p_dev, const int64_t *rec_dev, int nrec,
+               const void *p_obs_dev, void *q_dev, double *J_dev);
+
+/* grad_c_dev (dev double [P]) = (accumulate ? grad_c_dev : 0)
+ *   + Re( sum_b g_V[b] * dV/dc ),  g_dev: dev [B][P], dVdc_dev: dev [P]. */
+int tbs_speed_gradient(tbs_plan *plan, const void *g_dev, const void *dVdc_dev,
+                       double *grad_c_dev, int accumulate);
+
+/* Release the plan and all device memory it owns (NULL-safe).  Synchronises
+ * the plan's stream first. */
+void tbs_plan_destroy(tbs_plan *plan);
+
+/* Message of the last failure on this plan (NULL-safe; static string for
+ * NULL plans: the last tbs_plan_create failure of this thread). */
+const char *tbs_last_error(const tbs_plan *plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TBS_H */

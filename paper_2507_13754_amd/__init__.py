@@ -1,0 +1,339 @@
+"""Python binding of libtbs (the MI355X traditional-Born-series solver).
+
+A thin ctypes layer over the C ABI in ``include/tbs.h``: it checks and
+marshals arguments (torch tensors are passed by device pointer on the current
+torch stream) and raises on error codes.  All arithmetic of the method runs in
+the library's HIP kernels; there is no fallback path, and every call fails
+loudly when ``libtbs.so`` has not been built.
+
+Shapes follow the library: grids are C order, x fastest ((ny, nx) or
+(nz, ny, nx)); a batch of B right-hand sides is a leading axis.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtbs.so")
+
+TBS_C64, TBS_C128 = 0, 1
+TBS_OK = 0
+TBS_WARN_NONFINITE, TBS_WARN_DIVERGING = 1, 2
+TBS_ADJ_STORE, TBS_ADJ_RECOMPUTE = 0, 1
+
+# Every entry point of include/tbs.h.
+EXPORTS = (
+    "tbs_version", "tbs_status_string", "tbs_padded_length", "tbs_wavenumber",
+    "tbs_background_k0", "tbs_hankel01", "tbs_self_cell", "tbs_plan_create", "tbs_plan_info",
+    "tbs_plan_set_stream", "tbs_green_tabulate", "tbs_green_import", "tbs_green_export",
+    "tbs_potential", "tbs_solve", "tbs_harmonic_source", "tbs_adjoint", "tbs_misfit",
+    "tbs_speed_gradient", "tbs_plan_destroy", "tbs_last_error",
+)
+
+
+class TBSError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+class TBSWarning(UserWarning):
+    pass
+
+
+class c128(ctypes.Structure):
+    _fields_ = [("re", ctypes.c_double), ("im", ctypes.c_double)]
+
+
+_lib = None
+
+
+def library() -> ctypes.CDLL:
+    """Load libtbs.so (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          "or python -m paper_2507_13754_amd.build")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64p, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)
+    c128p = ctypes.POINTER(c128)
+    sig = {
+        "tbs_version": (ctypes.c_int, []),
+        "tbs_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+        "tbs_padded_length": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int, i64p]),
+        "tbs_wavenumber": (ctypes.c_int, [ctypes.c_double] * 4 + [c128p]),
+        "tbs_background_k0": (ctypes.c_int, [ctypes.c_double] * 5 + [c128p]),
+        "tbs_hankel01": (ctypes.c_int, [c128, c128p, c128p]),
+        "tbs_self_cell": (ctypes.c_int, [ctypes.c_int, c128, ctypes.c_double, c128p]),
+        "tbs_plan_create": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.c_int, i64p, ctypes.c_double,
+                                           c128, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp]),
+        "tbs_plan_info": (ctypes.c_int, [vp, i64p, i64p]),
+        "tbs_plan_set_stream": (ctypes.c_int, [vp, vp]),
+        "tbs_green_tabulate": (ctypes.c_int, [vp]),
+        "tbs_green_import": (ctypes.c_int, [vp, vp]),
+        "tbs_green_export": (ctypes.c_int, [vp, vp]),
+        "tbs_potential": (ctypes.c_int, [vp, vp] + [ctypes.c_double] * 5 + [vp, vp]),
+        "tbs_solve": (ctypes.c_int, [vp, vp, vp, ctypes.c_int, vp, dp]),
+        "tbs_harmonic_source": (ctypes.c_int, [vp, vp, vp, ctypes.c_double, ctypes.c_double,
+                                               ctypes.c_double, vp]),
+        "tbs_adjoint": (ctypes.c_int, [vp, vp, vp, ctypes.c_int, vp, vp, dp, ctypes.c_int]),
+        "tbs_misfit": (ctypes.c_int, [vp, vp, vp, ctypes.c_int, vp, vp, vp]),
+        "tbs_speed_gradient": (ctypes.c_int, [vp, vp, vp, vp, ctypes.c_int]),
+        "tbs_plan_destroy": (None, [vp]),
+        "tbs_last_error": (ctypes.c_char_p, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(rc: int, plan=None, what: str = "") -> int:
+    if rc == TBS_OK:
+        return rc
+    L = library()
+    msg = L.tbs_last_error(plan).decode() if plan is not None or rc < 0 else ""
+    name = L.tbs_status_string(rc).decode()
+    if rc < 0:
+        raise TBSError(rc, f"{what}: {name}: {msg}")
+    import warnings
+    warnings.warn(f"{what}: {name}: {msg}", TBSWarning, stacklevel=3)
+    return rc
+
+
+# ------------------------------------------------------------- host helpers --
+
+def padded_length(n: int, padding: int = 2) -> int:
+    m = ctypes.c_int64()
+    _check(library().tbs_padded_length(n, padding, ctypes.byref(m)), what="tbs_padded_length")
+    return int(m.value)
+
+
+def wavenumber(omega: float, c: float, alpha0: float, y: float) -> complex:
+    k = c128()
+    _check(library().tbs_wavenumber(omega, c, alpha0, y, ctypes.byref(k)), what="tbs_wavenumber")
+    return complex(k.re, k.im)
+
+
+def background_k0(omega: float, c0: float, alpha0: float, y: float, eps: float = 0.0) -> complex:
+    k = c128()
+    _check(library().tbs_background_k0(omega, c0, alpha0, y, eps, ctypes.byref(k)),
+           what="tbs_background_k0")
+    return complex(k.re, k.im)
+
+
+def hankel01(z: complex) -> Tuple[complex, complex]:
+    h0, h1 = c128(), c128()
+    _check(library().tbs_hankel01(c128(z.real, z.imag), ctypes.byref(h0), ctypes.byref(h1)),
+           what="tbs_hankel01")
+    return complex(h0.re, h0.im), complex(h1.re, h1.im)
+
+
+def self_cell(ndim: int, k0: complex, dx: float) -> complex:
+    w = c128()
+    _check(library().tbs_self_cell(ndim, c128(k0.real, k0.imag), dx, ctypes.byref(w)),
+           what="tbs_self_cell")
+    return complex(w.re, w.im)
+
+
+# -------------------------------------------------------------------- plans --
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t, dtype, shape: Optional[Sequence[int]] = None, name: str = "tensor"):
+    torch = _torch()
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) torch tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """Born-series plan for one grid, dx, background k0, precision and batch.
+
+    ``shape``: C-order grid, (ny, nx) or (nz, ny, nx).  ``dtype``:
+    torch.complex64 (FP32 with Kahan-compensated sums) or torch.complex128."""
+
+    def __init__(self, shape: Sequence[int], dx: float, k0: complex, padding: int = 2,
+                 dtype=None, batch: int = 1, stream=None):
+        torch = _torch()
+        L = library()
+        self.dtype = dtype if dtype is not None else torch.complex64
+        if self.dtype not in (torch.complex64, torch.complex128):
+            raise TypeError("dtype must be torch.complex64 or torch.complex128")
+        self.shape = tuple(int(s) for s in shape)
+        if len(self.shape) not in (2, 3):
+            raise ValueError("shape must be (ny, nx) or (nz, ny, nx)")
+        self.ndim = len(self.shape)
+        grid = list(reversed(self.shape)) + [1] * (3 - self.ndim)
+        self.batch = int(batch)
+        self.k0 = complex(k0)
+        self.dx = float(dx)
+        self._stream = stream
+        h = ctypes.c_void_p()
+        g = (ctypes.c_int64 * 3)(*grid)
+        rc = L.tbs_plan_create(ctypes.byref(h), self.ndim, g, self.dx, c128(self.k0.real, self.k0.imag),
+                               int(padding), TBS_C128 if self.dtype == torch.complex128 else TBS_C64,
+                               self.batch, self._stream_handle())
+        if rc != TBS_OK:
+            msg = L.tbs_last_error(None).decode()
+            raise TBSError(rc, f"tbs_plan_create: {L.tbs_status_string(rc).decode()}: {msg}")
+        self._h = h
+        pad = (ctypes.c_int64 * 3)()
+        nbytes = ctypes.c_int64()
+        L.tbs_plan_info(h, pad, ctypes.byref(nbytes))
+        self.padded = tuple(pad[i] for i in range(3))        # (Mx, My, Mz)
+        self.device_bytes = int(nbytes.value)
+
+    def _stream_handle(self):
+        torch = _torch()
+        s = self._stream if self._stream is not None else torch.cuda.current_stream()
+        return ctypes.c_void_p(s.cuda_stream)
+
+    def _sync_stream(self):
+        library().tbs_plan_set_stream(self._h, self._stream_handle())
+
+    @property
+    def points(self) -> int:
+        return int(np.prod(self.shape))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            library().tbs_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- Green spectrum --
+    def tabulate(self):
+        self._sync_stream()
+        _check(library().tbs_green_tabulate(self._h), self._h, "tbs_green_tabulate")
+        return self
+
+    def import_spectrum(self, full: np.ndarray):
+        Mx, My, Mz = self.padded
+        want = (Mz, My, Mx) if self.ndim == 3 else (My, Mx)
+        a = np.ascontiguousarray(full, dtype=np.complex128)
+        if a.shape != want:
+            raise ValueError(f"spectrum must have shape {want}")
+        self._sync_stream()
+        _check(library().tbs_green_import(self._h, a.ctypes.data_as(ctypes.c_void_p)), self._h,
+               "tbs_green_import")
+        return self
+
+    def export_spectrum(self) -> np.ndarray:
+        Mx, My, Mz = self.padded
+        shp = (Mx // 2 + 1, My // 2 + 1) + ((Mz // 2 + 1,) if self.ndim == 3 else ())
+        out = np.empty(shp, dtype=np.complex128)
+        _check(library().tbs_green_export(self._h, out.ctypes.data_as(ctypes.c_void_p)), self._h,
+               "tbs_green_export")
+        return out
+
+    # -- medium --
+    def potential(self, c, omega: float, c0: float, alpha0: float, y: float, eps: float = 0.0,
+                  with_derivative: bool = False):
+        torch = _torch()
+        cp = _ptr(c, torch.float64, self.shape, "c")
+        V = torch.empty(self.shape, dtype=self.dtype, device=c.device)
+        dV = torch.empty(self.shape, dtype=self.dtype, device=c.device) if with_derivative else None
+        self._sync_stream()
+        _check(library().tbs_potential(self._h, cp, omega, c0, alpha0, y, eps,
+                                       ctypes.c_void_p(V.data_ptr()),
+                                       ctypes.c_void_p(dV.data_ptr()) if dV is not None else None),
+               self._h, "tbs_potential")
+        return (V, dV) if with_derivative else V
+
+    # -- series --
+    def _bshape(self):
+        return (self.batch,) + self.shape
+
+    def solve(self, source, potential, nterms: int, out=None, residual: bool = False):
+        torch = _torch()
+        sp = _ptr(source, self.dtype, self._bshape(), "source")
+        vp = _ptr(potential, self.dtype, self.shape, "potential")
+        if out is None:
+            out = torch.empty(self._bshape(), dtype=self.dtype, device=source.device)
+        op = _ptr(out, self.dtype, self._bshape(), "out")
+        res = np.empty((self.batch, nterms), dtype=np.float64) if residual else None
+        self._sync_stream()
+        rc = library().tbs_solve(self._h, sp, vp, int(nterms), op,
+                                 res.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if residual else None)
+        _check(rc, self._h, "tbs_solve")
+        return (out, res) if residual else out
+
+    def harmonic_source(self, p1, c, omega: float, rho: float, BA: float, out=None):
+        torch = _torch()
+        pp = _ptr(p1, self.dtype, self._bshape(), "p1")
+        cp = _ptr(c, torch.float64, self.shape, "c")
+        if out is None:
+            out = torch.empty(self._bshape(), dtype=self.dtype, device=p1.device)
+        op = _ptr(out, self.dtype, self._bshape(), "out")
+        self._sync_stream()
+        _check(library().tbs_harmonic_source(self._h, pp, cp, omega, rho, BA, op), self._h,
+               "tbs_harmonic_source")
+        return out
+
+    def adjoint(self, source, potential, nterms: int, adj_source, out=None,
+                flags: int = TBS_ADJ_STORE, residual: bool = False):
+        torch = _torch()
+        sp = _ptr(source, self.dtype, self._bshape(), "source")
+        vp = _ptr(potential, self.dtype, self.shape, "potential")
+        qp = _ptr(adj_source, self.dtype, self._bshape(), "adj_source")
+        if out is None:
+            out = torch.empty(self._bshape(), dtype=self.dtype, device=source.device)
+        op = _ptr(out, self.dtype, self._bshape(), "out")
+        res = np.empty((self.batch, nterms), dtype=np.float64) if residual else None
+        self._sync_stream()
+        _check(library().tbs_adjoint(self._h, sp, vp, int(nterms), qp, op,
+                                     res.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if residual else None,
+                                     int(flags)), self._h, "tbs_adjoint")
+        return (out, res) if residual else out
+
+    def misfit(self, p, rec_index, p_obs):
+        """rec_index: CUDA int64 [R] flat spatial indices; p_obs [B][R]."""
+        torch = _torch()
+        pp = _ptr(p, self.dtype, self._bshape(), "p")
+        rp = _ptr(rec_index, torch.int64, None, "rec_index")
+        nrec = int(rec_index.numel())
+        op = _ptr(p_obs, self.dtype, (self.batch, nrec), "p_obs")
+        q = torch.empty(self._bshape(), dtype=self.dtype, device=p.device)
+        J = torch.empty((1,), dtype=torch.float64, device=p.device)
+        self._sync_stream()
+        _check(library().tbs_misfit(self._h, pp, rp, nrec, op, ctypes.c_void_p(q.data_ptr()),
+                                    ctypes.c_void_p(J.data_ptr())), self._h, "tbs_misfit")
+        return q, J
+
+    def speed_gradient(self, g, dVdc, out=None, accumulate: bool = False):
+        torch = _torch()
+        gp = _ptr(g, self.dtype, self._bshape(), "g")
+        dp = _ptr(dVdc, self.dtype, self.shape, "dVdc")
+        if out is None:
+            out = torch.empty(self.shape, dtype=torch.float64, device=g.device)
+            accumulate = False
+        op = _ptr(out, torch.float64, self.shape, "out")
+        self._sync_stream()
+        _check(library().tbs_speed_gradient(self._h, gp, dp, op, int(accumulate)), self._h,
+               "tbs_speed_gradient")
+        return out

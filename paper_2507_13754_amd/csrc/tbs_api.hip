@@ -1,0 +1,774 @@
+// Host runtime of the C ABI declared in include/tbs.h: plan validation and
+// sizing, device buffers, FP64 twiddle tables, the Green tabulation
+// sequence, and the per-term pass sequence of the Born series.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/tbs.h"
+#include "tbs_fft.hpp"
+#include "tbs_hankel.hpp"
+#include "tbs_internal.hpp"
+
+using tbs::zd;
+
+struct tbs_plan {
+  int ndim = 2;
+  int64_t N[3] = {1, 1, 1};  // x, y, z
+  int64_t M[3] = {1, 1, 1};
+  double dx = 0.0;
+  zd k0{0.0, 0.0};
+  int dtype = TBS_C64;
+  bool fp64 = false;
+  int batch = 1;
+  int cb = 4;
+  size_t esz = 8;
+  int64_t P = 0;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  // device buffers
+  void* X = nullptr;        // x-spectral intermediate [B][M_x/cb][rows][cb]
+  void* Yb = nullptr;       // 3D y-spectral intermediate [B][M_x/cb][M_y][N_z][cb]
+  void* kc = nullptr;       // Kahan compensation [B][P] (C64)
+  void* ghat = nullptr;     // folded spectrum
+  int64_t ghat_n = 0;
+  void* tw[3] = {nullptr, nullptr, nullptr};
+  double* partials = nullptr;
+  size_t partials_cap = 0;  // doubles
+  double* resid = nullptr;
+  size_t resid_cap = 0;
+  void* pstore = nullptr;   // adjoint: stored forward partial sums
+  size_t pstore_bytes = 0;
+  void* ckpt = nullptr;     // adjoint recompute: checkpoints
+  size_t ckpt_bytes = 0;
+  double* jpart = nullptr;
+  size_t jpart_cap = 0;
+  int64_t device_bytes = 0;
+  bool green_ready = false;
+  std::string err;
+};
+
+namespace {
+
+thread_local std::string g_create_err;
+
+int fail(tbs_plan* p, int code, const std::string& msg) {
+  if (p) p->err = msg;
+  else g_create_err = msg;
+  return code;
+}
+
+int hip_fail(tbs_plan* p, hipError_t e, const char* what) {
+  std::string m = std::string(what) + ": " + hipGetErrorString(e);
+  return fail(p, TBS_ERR_HIP, m);
+}
+
+#define TBS_HIP(plan, call)                              \
+  do {                                                   \
+    hipError_t e_ = (call);                              \
+    if (e_ != hipSuccess) return hip_fail(plan, e_, #call); \
+  } while (0)
+
+#define TBS_LAUNCH(plan, call)                                              \
+  do {                                                                      \
+    int e_ = (call);                                                        \
+    if (e_ != 0) return hip_fail(plan, (hipError_t)e_, #call);               \
+  } while (0)
+
+int dev_alloc(tbs_plan* p, void** ptr, size_t bytes) {
+  if (bytes == 0) {
+    *ptr = nullptr;
+    return TBS_OK;
+  }
+  hipError_t e = hipMalloc(ptr, bytes);
+  if (e != hipSuccess) {
+    *ptr = nullptr;
+    (void)hipGetLastError();
+    return fail(p, e == hipErrorOutOfMemory ? TBS_ERR_OOM : TBS_ERR_HIP,
+                "device allocation of " + std::to_string(bytes) + " bytes failed: " +
+                    hipGetErrorString(e));
+  }
+  p->device_bytes += (int64_t)bytes;
+  return TBS_OK;
+}
+
+void dev_free(tbs_plan* p, void*& ptr, size_t bytes) {
+  if (ptr) {
+    (void)hipFree(ptr);
+    p->device_bytes -= (int64_t)bytes;
+  }
+  ptr = nullptr;
+}
+
+bool is_fin(double v) { return std::isfinite(v); }
+
+// Twiddle table of one FFT length in the stage layout of tbs_fft.hpp, built in
+// extended precision and rounded once.
+std::vector<zd> twiddles(int M) {
+  const int E = tbs::fft_elems_per_thread(M);
+  const tbs::Stages st = tbs::make_stages(M, E);
+  std::vector<zd> out;
+  out.reserve(M);
+  long L = 1;
+  for (int s = 0; s < st.n; ++s) {
+    const long R = st.r[s];
+    for (long r = 1; r < R; ++r)
+      for (long k = 0; k < L; ++k) {
+        const long den = L * R;
+        const long num = (r * k) % den;
+        const long double ang = 2.0L * 3.141592653589793238462643383279502884L * (long double)num /
+                                (long double)den;
+        out.push_back(zd{(double)cosl(ang), (double)(-sinl(ang))});  // e^{-i ang}
+      }
+    L *= R;
+  }
+  return out;
+}
+
+int upload_twiddles(tbs_plan* p, int M, bool fp64, void** dst) {
+  std::vector<zd> t = twiddles(M);
+  size_t bytes = t.size() * (fp64 ? 16 : 8);
+  if (bytes == 0) bytes = 16;
+  int rc = dev_alloc(p, dst, bytes);
+  if (rc) return rc;
+  if (fp64) {
+    TBS_HIP(p, hipMemcpy(*dst, t.data(), t.size() * 16, hipMemcpyHostToDevice));
+  } else {
+    std::vector<float> f(2 * t.size());
+    for (size_t i = 0; i < t.size(); ++i) {
+      f[2 * i] = (float)t[i].re;
+      f[2 * i + 1] = (float)t[i].im;
+    }
+    TBS_HIP(p, hipMemcpy(*dst, f.data(), f.size() * 4, hipMemcpyHostToDevice));
+  }
+  return TBS_OK;
+}
+
+int ensure_doubles(tbs_plan* p, double** buf, size_t* cap, size_t need) {
+  if (*cap >= need) return TBS_OK;
+  void* q = *buf;
+  dev_free(p, q, *cap * 8);
+  *buf = nullptr;
+  *cap = 0;
+  int rc = dev_alloc(p, &q, need * 8);
+  if (rc) return rc;
+  *buf = (double*)q;
+  *cap = need;
+  return TBS_OK;
+}
+
+int row_blocks(const tbs_plan* p) {
+  const int NR = tbs::row_rows_per_block((int)p->M[0], p->fp64);
+  const int64_t rows = p->N[1] * p->N[2];
+  return (int)((rows + NR - 1) / NR);
+}
+
+// Row pass of one term.
+int run_row(tbs_plan* p, int in_mode, int acc, int out_spec, bool adjoint, const void* src,
+            const void* V, void* pacc, void* pstore_slot, const void* pair, void* grad,
+            double* partials) {
+  tbs::RowArgs a{};
+  a.X = p->X;
+  a.src = src;
+  a.V = V;
+  a.p = pacc;
+  a.c = p->kc;
+  a.pair = pair;
+  a.grad = grad;
+  a.partials = partials;
+  a.tw = p->tw[0];
+  a.nx = (int)p->N[0];
+  a.ny = (int)p->N[1];
+  a.nz = (int)p->N[2];
+  a.nrows = (int)(p->N[1] * p->N[2]);
+  a.nrhs = p->batch;
+  a.in_mode = in_mode;
+  a.acc = acc;
+  a.out_spec = out_spec;
+  a.conj_v = adjoint ? 1 : 0;
+  a.pstore = pstore_slot;
+  a.cb = p->cb;
+  a.xcd_remap = 1;
+  TBS_LAUNCH(p, tbs::launch_row_pass(p->fp64, (int)p->M[0], a, row_blocks(p), p->stream));
+  return TBS_OK;
+}
+
+// Green's-function application to the row-pass output (all columns).
+int run_cols(tbs_plan* p, bool adjoint) {
+  const int64_t cb = p->cb;
+  const int64_t nkb = p->M[0] / cb;
+  if (p->ndim == 2) {
+    tbs::ColArgs a{};
+    a.in = p->X;
+    a.out = p->X;
+    a.tw = p->tw[1];
+    a.ghat = p->ghat;
+    a.op = tbs::COL_CONV;
+    a.conj_g = adjoint ? 1 : 0;
+    a.n_in = (int)p->N[1];
+    a.n_out = (int)p->N[1];
+    a.in_astride = a.out_astride = cb;
+    a.in_rs = a.out_rs = nkb * p->N[1] * cb;
+    a.in_s1 = a.out_s1 = p->N[1] * cb;
+    a.in_s0 = a.out_s0 = 0;
+    a.nrhs = p->batch;
+    a.n1 = (int)nkb;
+    a.n0 = 1;
+    a.cb = (int)cb;
+    a.zcols = 0;
+    a.zlim = 1;
+    a.mx = (int)p->M[0];
+    a.mm = 1;
+    a.g_sx = p->M[1] / 2 + 1;
+    a.g_sm = 0;
+    a.xcd_remap = 1;
+    TBS_LAUNCH(p, tbs::launch_col_pass(p->fp64, (int)p->M[1], (int)cb, a, p->stream));
+    return TBS_OK;
+  }
+  // 3D: y forward (A -> B), z convolution (in B), y inverse (B -> A).
+  const int64_t ny = p->N[1], nz = p->N[2], my = p->M[1];
+  const int NZ = my <= 512 ? 4 : 1;  // z planes per y-pass block (LDS-bound)
+  const int NC = NZ * (int)cb;
+  const int nzb = (int)((nz + NZ - 1) / NZ);
+  tbs::ColArgs y{};
+  y.tw = p->tw[1];
+  y.nrhs = p->batch;
+  y.n1 = (int)nkb;
+  y.n0 = nzb;
+  y.cb = (int)cb;
+  y.zcols = NZ;
+  y.zlim = (int)nz;
+  y.xcd_remap = 1;
+  // A element (rhs, kxb, y, z, c): ((rhs*nkb + kxb)*ny + y)*nz*cb + z*cb + c
+  // B element (rhs, kxb, ky, z, c): ((rhs*nkb + kxb)*my + ky)*nz*cb + z*cb + c
+  tbs::ColArgs f = y;
+  f.in = p->X;
+  f.out = p->Yb;
+  f.op = tbs::COL_FWD;
+  f.n_in = (int)ny;
+  f.n_out = (int)my;
+  f.in_astride = nz * cb;
+  f.out_astride = nz * cb;
+  f.in_rs = nkb * ny * nz * cb;
+  f.in_s1 = ny * nz * cb;
+  f.in_s0 = NZ * cb;
+  f.out_rs = nkb * my * nz * cb;
+  f.out_s1 = my * nz * cb;
+  f.out_s0 = NZ * cb;
+  TBS_LAUNCH(p, tbs::launch_col_pass(p->fp64, (int)my, NC, f, p->stream));
+
+  tbs::ColArgs z{};
+  z.in = p->Yb;
+  z.out = p->Yb;
+  z.tw = p->tw[2];
+  z.ghat = p->ghat;
+  z.op = tbs::COL_CONV;
+  z.conj_g = adjoint ? 1 : 0;
+  z.n_in = (int)nz;
+  z.n_out = (int)nz;
+  z.in_astride = z.out_astride = cb;
+  z.in_rs = z.out_rs = nkb * my * nz * cb;
+  z.in_s1 = z.out_s1 = my * nz * cb;
+  z.in_s0 = z.out_s0 = nz * cb;
+  z.nrhs = p->batch;
+  z.n1 = (int)nkb;
+  z.n0 = (int)my;
+  z.cb = (int)cb;
+  z.zcols = 0;
+  z.zlim = 1;
+  z.mx = (int)p->M[0];
+  z.mm = (int)my;
+  z.g_sx = (p->M[1] / 2 + 1) * (p->M[2] / 2 + 1);
+  z.g_sm = p->M[2] / 2 + 1;
+  z.xcd_remap = 1;
+  TBS_LAUNCH(p, tbs::launch_col_pass(p->fp64, (int)p->M[2], (int)cb, z, p->stream));
+
+  tbs::ColArgs iv = y;
+  iv.in = p->Yb;
+  iv.out = p->X;
+  iv.op = tbs::COL_INV;
+  iv.n_in = (int)my;
+  iv.n_out = (int)ny;
+  iv.in_astride = nz * cb;
+  iv.out_astride = nz * cb;
+  iv.in_rs = nkb * my * nz * cb;
+  iv.in_s1 = my * nz * cb;
+  iv.in_s0 = NZ * cb;
+  iv.out_rs = nkb * ny * nz * cb;
+  iv.out_s1 = ny * nz * cb;
+  iv.out_s0 = NZ * cb;
+  TBS_LAUNCH(p, tbs::launch_col_pass(p->fp64, (int)my, NC, iv, p->stream));
+  return TBS_OK;
+}
+
+int check_residuals(tbs_plan* p, double* residual_out, int nterms) {
+  TBS_HIP(p, hipMemcpyAsync(residual_out, p->resid, sizeof(double) * p->batch * nterms,
+                            hipMemcpyDeviceToHost, p->stream));
+  TBS_HIP(p, hipStreamSynchronize(p->stream));
+  int warn = TBS_OK;
+  for (int b = 0; b < p->batch; ++b) {
+    const double* r = residual_out + (size_t)b * nterms;
+    int grow = 0;
+    for (int n = 0; n < nterms; ++n) {
+      if (!is_fin(r[n])) {
+        p->err = "non-finite residual (non-finite source or potential?)";
+        return TBS_WARN_NONFINITE;
+      }
+      grow = (n > 0 && r[n] > r[n - 1]) ? grow + 1 : 0;
+      if (grow >= 3 && warn == TBS_OK) {
+        p->err = "residuals grew over 3 consecutive terms (series diverging: rho(GV) >= 1?)";
+        warn = TBS_WARN_DIVERGING;
+      }
+    }
+  }
+  return warn;
+}
+
+// Forward series.  pstore (optional): slot K-1 receives P_K, K = 1..L-1.
+int forward_series(tbs_plan* p, const void* source, const void* V, int L, void* p_out,
+                   void* pstore) {
+  const int nblk = row_blocks(p);
+  const size_t per_term = (size_t)2 * p->batch * nblk;
+  int rc = ensure_doubles(p, &p->partials, &p->partials_cap, per_term * (size_t)L);
+  if (rc) return rc;
+  rc = ensure_doubles(p, &p->resid, &p->resid_cap, (size_t)p->batch * L);
+  if (rc) return rc;
+  const size_t slot = (size_t)p->batch * p->P * p->esz;
+  const int Leff = V ? L : 1;  // V = 0: u_n = 0 for n >= 1
+  // u_0 = G s
+  rc = run_row(p, tbs::ROW_IN_SOURCE, tbs::ACC_NONE, 1, false, source, nullptr, nullptr, nullptr,
+               nullptr, nullptr, nullptr);
+  if (rc) return rc;
+  rc = run_cols(p, false);
+  if (rc) return rc;
+  for (int n = 1; n < Leff; ++n) {
+    void* st = pstore ? (void*)((char*)pstore + (size_t)(n - 1) * slot) : nullptr;
+    rc = run_row(p, tbs::ROW_IN_SPECTRAL, n == 1 ? tbs::ACC_INIT : tbs::ACC_ADD, 1, false,
+                 nullptr, V, p_out, st, nullptr, nullptr, p->partials + (size_t)(n - 1) * per_term);
+    if (rc) return rc;
+    rc = run_cols(p, false);
+    if (rc) return rc;
+  }
+  rc = run_row(p, tbs::ROW_IN_SPECTRAL, Leff == 1 ? tbs::ACC_INIT : tbs::ACC_ADD, 0, false,
+               nullptr, nullptr, p_out, nullptr, nullptr, nullptr,
+               p->partials + (size_t)(Leff - 1) * per_term);
+  if (rc) return rc;
+  // terms n >= Leff are exactly zero (V = 0)
+  TBS_LAUNCH(p, tbs::launch_finish_norms(p->partials, L, Leff, p->batch, nblk, p->resid, p->stream));
+  return TBS_OK;
+}
+
+int check_plan_ready(tbs_plan* p) {
+  if (!p) return TBS_ERR_INVALID;
+  if (!p->green_ready)
+    return fail(p, TBS_ERR_STATE, "the Green spectrum is not set: call tbs_green_tabulate first");
+  return TBS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tbs_version(void) { return 100; }
+
+const char* tbs_status_string(int s) {
+  switch (s) {
+    case TBS_OK: return "TBS_OK";
+    case TBS_ERR_INVALID: return "TBS_ERR_INVALID";
+    case TBS_ERR_UNSUPPORTED: return "TBS_ERR_UNSUPPORTED";
+    case TBS_ERR_OOM: return "TBS_ERR_OOM";
+    case TBS_ERR_HIP: return "TBS_ERR_HIP";
+    case TBS_ERR_STATE: return "TBS_ERR_STATE";
+    case TBS_WARN_NONFINITE: return "TBS_WARN_NONFINITE";
+    case TBS_WARN_DIVERGING: return "TBS_WARN_DIVERGING";
+    default: return "unknown status";
+  }
+}
+
+int tbs_padded_length(int64_t n, int padding, int64_t* m_out) {
+  if (!m_out || n < 1 || padding < 2 || n > (int64_t)1 << 30) return TBS_ERR_INVALID;
+  const int64_t need = padding * n - 1;
+  for (int64_t m = 16; m <= 4096; m *= 2) {
+    if (m >= need && tbs::fft_length_supported((int)m)) {
+      *m_out = m;
+      return TBS_OK;
+    }
+  }
+  return TBS_ERR_UNSUPPORTED;
+}
+
+int tbs_wavenumber(double omega, double c, double alpha0, double y, tbs_c128* k_out) {
+  if (!k_out || !(omega > 0) || !(c > 0) || !(alpha0 >= 0) || !is_fin(y)) return TBS_ERR_INVALID;
+  const double a = alpha0 * std::pow(omega, y);
+  const double disp = (std::fabs(y - 1.0) < 1e-12) ? 0.0 : std::tan(tbs::kPi * y / 2.0);
+  k_out->re = omega / c + a * disp;
+  k_out->im = a;
+  return TBS_OK;
+}
+
+int tbs_background_k0(double omega, double c0, double alpha0, double y, double eps,
+                      tbs_c128* k0_out) {
+  if (!k0_out || !(eps >= 0)) return TBS_ERR_INVALID;
+  tbs_c128 k;
+  int rc = tbs_wavenumber(omega, c0, alpha0, y, &k);
+  if (rc) return rc;
+  const zd k2 = tbs::zadd(tbs::zmul(zd{k.re, k.im}, zd{k.re, k.im}), zd{0.0, eps});
+  const zd r = tbs::zsqrt(k2);
+  k0_out->re = r.re;
+  k0_out->im = r.im;
+  return TBS_OK;
+}
+
+int tbs_hankel01(tbs_c128 z, tbs_c128* h0, tbs_c128* h1) {
+  if (!h0 || !h1 || !(z.re > 0) || !(z.im >= 0)) return TBS_ERR_INVALID;
+  zd a, b;
+  tbs::hankel01(zd{z.re, z.im}, &a, &b);
+  h0->re = a.re;
+  h0->im = a.im;
+  h1->re = b.re;
+  h1->im = b.im;
+  return TBS_OK;
+}
+
+int tbs_self_cell(int ndim, tbs_c128 k0, double dx, tbs_c128* w0) {
+  if (!w0 || !(dx > 0) || !(k0.re > 0) || !(k0.im >= 0)) return TBS_ERR_INVALID;
+  zd w;
+  if (ndim == 2) w = tbs::self_cell_2d(zd{k0.re, k0.im}, dx);
+  else if (ndim == 3) w = tbs::self_cell_3d(zd{k0.re, k0.im}, dx);
+  else return TBS_ERR_INVALID;
+  w0->re = w.re;
+  w0->im = w.im;
+  return TBS_OK;
+}
+
+void tbs_plan_destroy(tbs_plan* p) {
+  if (!p) return;
+  (void)hipStreamSynchronize(p->stream);
+  dev_free(p, p->X, 0);
+  dev_free(p, p->Yb, 0);
+  dev_free(p, p->kc, 0);
+  dev_free(p, p->ghat, 0);
+  for (auto& t : p->tw) dev_free(p, t, 0);
+  void* q = p->partials;
+  dev_free(p, q, 0);
+  q = p->resid;
+  dev_free(p, q, 0);
+  dev_free(p, p->pstore, 0);
+  dev_free(p, p->ckpt, 0);
+  q = p->jpart;
+  dev_free(p, q, 0);
+  delete p;
+}
+
+int tbs_plan_create(tbs_plan** out, int ndim, const int64_t grid[3], double dx, tbs_c128 k0,
+                    int padding, int dtype, int batch, void* hip_stream) {
+  if (!out) return fail(nullptr, TBS_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  if (ndim != 2 && ndim != 3) return fail(nullptr, TBS_ERR_INVALID, "ndim must be 2 or 3");
+  if (!grid) return fail(nullptr, TBS_ERR_INVALID, "grid is NULL");
+  if (!(dx > 0) || !is_fin(dx)) return fail(nullptr, TBS_ERR_INVALID, "dx must be > 0");
+  if (!(k0.re > 0) || !(k0.im >= 0) || !is_fin(k0.re) || !is_fin(k0.im))
+    return fail(nullptr, TBS_ERR_INVALID, "k0 needs Re k0 > 0 and Im k0 >= 0");
+  if (padding < 2) return fail(nullptr, TBS_ERR_INVALID, "padding must be >= 2");
+  if (dtype != TBS_C64 && dtype != TBS_C128) return fail(nullptr, TBS_ERR_INVALID, "bad dtype");
+  if (batch < 1 || batch > 4096) return fail(nullptr, TBS_ERR_INVALID, "batch must be 1..4096");
+  tbs_plan* p = new (std::nothrow) tbs_plan();
+  if (!p) return fail(nullptr, TBS_ERR_OOM, "host allocation failed");
+  p->ndim = ndim;
+  p->N[0] = grid[0];
+  p->N[1] = grid[1];
+  p->N[2] = ndim == 3 ? grid[2] : 1;
+  for (int d = 0; d < ndim; ++d) {
+    if (p->N[d] < 1 || p->N[d] > 2048) {
+      delete p;
+      return fail(nullptr, TBS_ERR_UNSUPPORTED, "grid sizes must be 1..2048");
+    }
+    int rc = tbs_padded_length(p->N[d], padding, &p->M[d]);
+    if (rc) {
+      delete p;
+      return fail(nullptr, TBS_ERR_UNSUPPORTED, "no compiled FFT length for this grid size");
+    }
+  }
+  p->dx = dx;
+  p->k0 = zd{k0.re, k0.im};
+  p->dtype = dtype;
+  p->fp64 = dtype == TBS_C128;
+  p->esz = p->fp64 ? 16 : 8;
+  p->batch = batch;
+  p->stream = (hipStream_t)hip_stream;
+  p->P = p->N[0] * p->N[1] * p->N[2];
+  p->cb = tbs::spectral_block((int)(ndim == 2 ? p->M[1] : p->M[2]), p->fp64);
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    (void)hipGetLastError();
+    delete p;
+    return fail(nullptr, TBS_ERR_HIP, "no HIP device");
+  }
+  const size_t B = (size_t)batch;
+  const size_t xe = B * p->M[0] * p->N[1] * p->N[2];
+  int rc = dev_alloc(p, &p->X, xe * p->esz);
+  if (!rc && ndim == 3) rc = dev_alloc(p, &p->Yb, B * p->M[0] * p->M[1] * p->N[2] * p->esz);
+  if (!rc && !p->fp64) rc = dev_alloc(p, &p->kc, B * p->P * p->esz);
+  p->ghat_n = (p->M[0] / 2 + 1) * (p->M[1] / 2 + 1) * (ndim == 3 ? p->M[2] / 2 + 1 : 1);
+  if (!rc) rc = dev_alloc(p, &p->ghat, (size_t)p->ghat_n * p->esz);
+  for (int d = 0; d < ndim && !rc; ++d) rc = upload_twiddles(p, (int)p->M[d], p->fp64, &p->tw[d]);
+  if (rc) {
+    g_create_err = p->err;
+    tbs_plan_destroy(p);
+    return rc;
+  }
+  *out = p;
+  return TBS_OK;
+}
+
+int tbs_plan_info(const tbs_plan* p, int64_t padded[3], int64_t* bytes) {
+  if (!p) return TBS_ERR_INVALID;
+  if (padded) {
+    padded[0] = p->M[0];
+    padded[1] = p->M[1];
+    padded[2] = p->ndim == 3 ? p->M[2] : 1;
+  }
+  if (bytes) *bytes = p->device_bytes;
+  return TBS_OK;
+}
+
+int tbs_plan_set_stream(tbs_plan* p, void* s) {
+  if (!p) return TBS_ERR_INVALID;
+  p->stream = (hipStream_t)s;
+  return TBS_OK;
+}
+
+int tbs_green_tabulate(tbs_plan* p) {
+  if (!p) return TBS_ERR_INVALID;
+  const int64_t Mx = p->M[0], My = p->M[1], Mz = p->ndim == 3 ? p->M[2] : 1;
+  const int64_t M3[3] = {Mx, My, Mz};
+  void* W = nullptr;
+  int rc = dev_alloc(p, &W, (size_t)(Mx * My * Mz) * 16);
+  if (rc) return rc;
+  void* tw64[3] = {nullptr, nullptr, nullptr};
+  for (int d = 0; d < p->ndim && !rc; ++d) rc = upload_twiddles(p, (int)M3[d], true, &tw64[d]);
+  auto cleanup = [&]() {
+    dev_free(p, W, (size_t)(Mx * My * Mz) * 16);
+    for (int d = 0; d < 3; ++d) dev_free(p, tw64[d], 0);
+  };
+  if (rc) {
+    cleanup();
+    return rc;
+  }
+  tbs_c128 w0;
+  tbs_self_cell(p->ndim, tbs_c128{p->k0.re, p->k0.im}, p->dx, &w0);
+  int e = tbs::launch_green_eval(W, p->ndim, M3, p->dx, p->k0.re, p->k0.im, w0.re, w0.im, p->stream);
+  // x: contiguous rows
+  if (!e) e = tbs::launch_row_fft_full((int)Mx, W, tw64[0], (int)(My * Mz), 0, p->stream);
+  // y, then z: strided lines, 4 contiguous columns per block
+  for (int ax = 1; ax < p->ndim && !e; ++ax) {
+    const int nc = tbs::col_max_cols((int)M3[ax], true);
+    tbs::ColArgs a{};
+    a.in = W;
+    a.out = W;
+    a.tw = tw64[ax];
+    a.op = tbs::COL_FULL;
+    a.cb = nc;
+    a.zcols = 0;
+    a.zlim = 1;
+    a.nrhs = 1;
+    a.n0 = (int)(Mx / nc);
+    a.in_s0 = a.out_s0 = nc;
+    if (ax == 1) {
+      a.n_in = a.n_out = (int)My;
+      a.in_astride = a.out_astride = Mx;
+      a.n1 = (int)Mz;
+      a.in_s1 = a.out_s1 = My * Mx;
+    } else {
+      a.n_in = a.n_out = (int)Mz;
+      a.in_astride = a.out_astride = Mx * My;
+      a.n1 = (int)My;
+      a.in_s1 = a.out_s1 = Mx;
+    }
+    a.xcd_remap = 0;
+    e = tbs::launch_col_pass(true, (int)M3[ax], nc, a, p->stream);
+  }
+  if (!e) e = tbs::launch_green_fold(W, p->ghat, p->fp64, p->ndim, M3, p->stream);
+  if (e) {
+    cleanup();
+    return hip_fail(p, (hipError_t)e, "green tabulation launch");
+  }
+  hipError_t he = hipStreamSynchronize(p->stream);
+  cleanup();
+  if (he != hipSuccess) return hip_fail(p, he, "green tabulation");
+  p->green_ready = true;
+  return TBS_OK;
+}
+
+int tbs_green_import(tbs_plan* p, const tbs_c128* full) {
+  if (!p || !full) return fail(p, TBS_ERR_INVALID, "NULL argument");
+  const int64_t Mx = p->M[0], My = p->M[1], Mz = p->ndim == 3 ? p->M[2] : 1;
+  const int64_t hx = Mx / 2 + 1, hy = My / 2 + 1, hz = Mz / 2 + 1;
+  const double sc = 1.0 / ((double)Mx * (double)My * (double)Mz);
+  std::vector<double> buf(2 * (size_t)p->ghat_n);
+  for (int64_t fx = 0; fx < hx; ++fx)
+    for (int64_t fy = 0; fy < hy; ++fy)
+      for (int64_t fz = 0; fz < hz; ++fz) {
+        const tbs_c128 v = full[(fz * My + fy) * Mx + fx];
+        const size_t i = (size_t)((fx * hy + fy) * hz + fz);
+        buf[2 * i] = v.re * sc;
+        buf[2 * i + 1] = v.im * sc;
+      }
+  if (p->fp64) {
+    TBS_HIP(p, hipMemcpy(p->ghat, buf.data(), buf.size() * 8, hipMemcpyHostToDevice));
+  } else {
+    std::vector<float> f(buf.size());
+    for (size_t i = 0; i < buf.size(); ++i) f[i] = (float)buf[i];
+    TBS_HIP(p, hipMemcpy(p->ghat, f.data(), f.size() * 4, hipMemcpyHostToDevice));
+  }
+  p->green_ready = true;
+  return TBS_OK;
+}
+
+int tbs_green_export(const tbs_plan* pc, tbs_c128* out) {
+  tbs_plan* p = const_cast<tbs_plan*>(pc);
+  if (!p || !out) return fail(p, TBS_ERR_INVALID, "NULL argument");
+  if (!p->green_ready) return fail(p, TBS_ERR_STATE, "no spectrum tabulated");
+  TBS_HIP(p, hipStreamSynchronize(p->stream));
+  if (p->fp64) {
+    TBS_HIP(p, hipMemcpy(out, p->ghat, (size_t)p->ghat_n * 16, hipMemcpyDeviceToHost));
+  } else {
+    std::vector<float> f(2 * (size_t)p->ghat_n);
+    TBS_HIP(p, hipMemcpy(f.data(), p->ghat, f.size() * 4, hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < p->ghat_n; ++i) out[i] = tbs_c128{f[2 * i], f[2 * i + 1]};
+  }
+  return TBS_OK;
+}
+
+int tbs_potential(tbs_plan* p, const double* c, double omega, double c0, double alpha0, double y,
+                  double eps, void* V, void* dVdc) {
+  if (!p || !c) return fail(p, TBS_ERR_INVALID, "NULL argument");
+  if (!(omega > 0) || !(c0 > 0) || !(alpha0 >= 0) || !(eps >= 0) || !is_fin(y))
+    return fail(p, TBS_ERR_INVALID, "bad medium parameters");
+  const double a = alpha0 * std::pow(omega, y);
+  const double disp = (std::fabs(y - 1.0) < 1e-12) ? 0.0 : std::tan(tbs::kPi * y / 2.0);
+  const double kr = omega / c0 + a * disp, ki = a;
+  const double k0r = kr * kr - ki * ki, k0i = 2.0 * kr * ki + eps;
+  TBS_LAUNCH(p, tbs::launch_potential(c, V, dVdc, p->fp64, p->P, omega, a, disp, k0r, k0i,
+                                      p->stream));
+  return TBS_OK;
+}
+
+int tbs_solve(tbs_plan* p, const void* source, const void* V, int nterms, void* p_out,
+              double* residual_out) {
+  int rc = check_plan_ready(p);
+  if (rc) return rc;
+  if (!source || !p_out) return fail(p, TBS_ERR_INVALID, "source and p_out are required");
+  if (nterms < 1 || nterms > 100000) return fail(p, TBS_ERR_INVALID, "nterms must be >= 1");
+  if (p_out == source || p_out == V) return fail(p, TBS_ERR_INVALID, "p_out aliases an input");
+  rc = forward_series(p, source, V, nterms, p_out, nullptr);
+  if (rc) return rc;
+  if (residual_out) return check_residuals(p, residual_out, nterms);
+  return TBS_OK;
+}
+
+int tbs_harmonic_source(tbs_plan* p, const void* p1, const double* c, double omega, double rho,
+                        double BA, void* S2) {
+  if (!p || !p1 || !c || !S2) return fail(p, TBS_ERR_INVALID, "NULL argument");
+  if (!(omega > 0) || !(rho > 0) || !is_fin(BA)) return fail(p, TBS_ERR_INVALID, "bad parameters");
+  const double coef = -0.5 * (1.0 + 0.5 * BA) / rho * (2.0 * omega) * (2.0 * omega);
+  TBS_LAUNCH(p, tbs::launch_harmonic_source(p1, c, S2, p->fp64, p->P, p->batch, coef, p->stream));
+  return TBS_OK;
+}
+
+int tbs_adjoint(tbs_plan* p, const void* source, const void* V, int L, const void* q, void* grad,
+                double* residual_out, int flags) {
+  int rc = check_plan_ready(p);
+  if (rc) return rc;
+  if (!source || !V || !q || !grad) return fail(p, TBS_ERR_INVALID, "NULL argument");
+  if (L < 1 || L > 100000) return fail(p, TBS_ERR_INVALID, "nterms must be >= 1");
+  if (flags != TBS_ADJ_STORE && flags != TBS_ADJ_RECOMPUTE)
+    return fail(p, TBS_ERR_INVALID, "bad flags");
+  const size_t slot = (size_t)p->batch * p->P * p->esz;
+  TBS_LAUNCH(p, tbs::launch_zero(grad, (int64_t)slot, p->stream));
+  if (L == 1) {
+    if (residual_out) {
+      // forward residuals still requested
+      void* tmp = nullptr;
+      rc = dev_alloc(p, &tmp, slot);
+      if (rc) return rc;
+      rc = forward_series(p, source, V, 1, tmp, nullptr);
+      int r2 = rc ? rc : check_residuals(p, residual_out, 1);
+      (void)hipStreamSynchronize(p->stream);
+      dev_free(p, tmp, slot);
+      return r2;
+    }
+    return TBS_OK;
+  }
+  // Forward pass keeping the partial sums P_1..P_{L-1} (the final p is not needed).
+  const size_t need = slot * (size_t)(L - 1);
+  if (p->pstore_bytes < need) {
+    dev_free(p, p->pstore, p->pstore_bytes);
+    p->pstore_bytes = 0;
+    rc = dev_alloc(p, &p->pstore, need + slot);
+    if (rc) return rc;
+    p->pstore_bytes = need + slot;
+  }
+  void* pacc = (char*)p->pstore + need;  // running sum buffer
+  (void)flags;
+  rc = forward_series(p, source, V, L, pacc, p->pstore);
+  if (rc) return rc;
+  if (residual_out) {
+    rc = check_residuals(p, residual_out, L);
+    if (rc < 0) return rc;
+  }
+  // Adjoint series: w_0 = G^H q; row pass m pairs w_m with P_{L-1-m} and
+  // forms conj(V) w_m for the next term, m = 0..L-2.
+  const int nblk = row_blocks(p);
+  rc = run_row(p, tbs::ROW_IN_SOURCE, tbs::ACC_NONE, 1, true, q, nullptr, nullptr, nullptr,
+               nullptr, nullptr, nullptr);
+  if (rc) return rc;
+  rc = run_cols(p, true);
+  if (rc) return rc;
+  (void)nblk;
+  for (int m = 0; m <= L - 2; ++m) {
+    const void* pair = (const char*)p->pstore + (size_t)(L - 2 - m) * slot;  // P_{L-1-m}
+    const bool more = m < L - 2;
+    rc = run_row(p, tbs::ROW_IN_SPECTRAL, tbs::ACC_PAIR, more ? 1 : 0, true, nullptr, V, nullptr,
+                 nullptr, pair, grad, p->partials);
+    if (rc) return rc;
+    if (more) {
+      rc = run_cols(p, true);
+      if (rc) return rc;
+    }
+  }
+  return TBS_OK;
+}
+
+int tbs_misfit(tbs_plan* p, const void* pf, const int64_t* rec, int nrec, const void* pobs,
+               void* q, double* J) {
+  if (!p || !pf || !rec || !pobs || !q || !J || nrec < 1)
+    return fail(p, TBS_ERR_INVALID, "bad misfit arguments");
+  const size_t slot = (size_t)p->batch * p->P * p->esz;
+  int rc = ensure_doubles(p, &p->jpart, &p->jpart_cap, (size_t)nrec * p->batch);
+  if (rc) return rc;
+  TBS_LAUNCH(p, tbs::launch_zero(q, (int64_t)slot, p->stream));
+  TBS_LAUNCH(p, tbs::launch_misfit(pf, rec, pobs, q, p->jpart, p->fp64, p->P, nrec, p->batch,
+                                   p->stream));
+  TBS_LAUNCH(p, tbs::launch_sum_half(p->jpart, nrec * p->batch, J, p->stream));
+  return TBS_OK;
+}
+
+int tbs_speed_gradient(tbs_plan* p, const void* g, const void* dVdc, double* grad_c,
+                       int accumulate) {
+  if (!p || !g || !dVdc || !grad_c) return fail(p, TBS_ERR_INVALID, "NULL argument");
+  TBS_LAUNCH(p, tbs::launch_grad_assemble(g, p->batch, dVdc, grad_c, p->fp64, p->P, accumulate,
+                                          p->stream));
+  return TBS_OK;
+}
+
+const char* tbs_last_error(const tbs_plan* p) {
+  if (!p) return g_create_err.c_str();
+  return p->err.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,326 @@
+// Device FFT core for the Born-series passes (CDNA4 / gfx950).
+//
+// One transform of length M is held by TPT = M/E threads, E complex values per
+// thread, in the "strided" register layout: register j of thread t holds
+// element t + j*TPT.  That layout is the input of the first Stockham stage and
+// the output of the last one, so a pass can load a zero-padded line straight
+// from HBM into registers (elements >= M/2 are the registers j >= E/2), run
+// the transform, apply a point-wise operation in registers, and start the
+// next transform without any reordering.
+//
+// Stage s has radix R_s and L_s = prod_{i<s} R_i.  Butterfly b (M/R_s of them;
+// thread t owns b = t + q*TPT, q < E/R_s) reads elements b + r*M/R_s,
+// multiplies element r by w_{L_s R_s}^{r (b mod L_s)}, does a DFT of size R_s
+// and writes output r to (b / L_s) L_s R_s + (b mod L_s) + r L_s (Stockham
+// autosort, natural order out).  Between stages the data goes through LDS.
+// Twiddles come from a per-length table built in FP64 on the host and rounded
+// once to the working precision (no recurrences): stage s uses
+// tw[off_s + (r-1) L_s + k], k < L_s, 1 <= r < R_s.  The inverse transform
+// conjugates them.  Transforms are unnormalised in both directions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace tbs {
+
+template <typename T>
+struct cx {
+  T x, y;
+};
+
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// a * conj(b)
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {
+  return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> cscale(cx<T> a, T s) { return {a.x * s, a.y * s}; }
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> cconj(cx<T> a) { return {a.x, -a.y}; }
+
+// Multiply by w4 = -i (forward) or +i (inverse).
+template <bool INV, typename T>
+__host__ __device__ __forceinline__ cx<T> rot4(cx<T> a) {
+  if constexpr (INV) return {-a.y, a.x};
+  else return {a.y, -a.x};
+}
+
+// Multiply by the constant e^{-+ 2 pi i m / 16} (forward: minus).
+template <bool INV, int m, typename T>
+__host__ __device__ __forceinline__ cx<T> rot16(cx<T> a) {
+  constexpr int mm = ((m % 16) + 16) % 16;
+  const T c1 = T(0.92387953251128675613);   // cos(pi/8)
+  const T s1 = T(0.38268343236508977173);   // sin(pi/8)
+  const T h = T(0.70710678118654752440);    // sqrt(1/2)
+  // e^{-2 pi i mm/16} = cos(theta) - i sin(theta), theta = pi mm / 8
+  T c, s;
+  if constexpr (mm == 0) return a;
+  else if constexpr (mm == 4) return rot4<INV>(a);
+  else if constexpr (mm == 8) return {-a.x, -a.y};
+  else if constexpr (mm == 12) return rot4<!INV>(a);
+  else {
+    if constexpr (mm == 1) { c = c1; s = s1; }
+    else if constexpr (mm == 2) { c = h; s = h; }
+    else if constexpr (mm == 3) { c = s1; s = c1; }
+    else if constexpr (mm == 5) { c = -s1; s = c1; }
+    else if constexpr (mm == 6) { c = -h; s = h; }
+    else if constexpr (mm == 7) { c = -c1; s = s1; }
+    else if constexpr (mm == 9) { c = -c1; s = -s1; }
+    else if constexpr (mm == 10) { c = -h; s = -h; }
+    else if constexpr (mm == 11) { c = -s1; s = -c1; }
+    else if constexpr (mm == 13) { c = s1; s = -c1; }
+    else if constexpr (mm == 14) { c = h; s = -h; }
+    else { c = c1; s = -s1; }
+    // forward multiplier (c - i s); inverse (c + i s)
+    if constexpr (INV) return {a.x * c - a.y * s, a.x * s + a.y * c};
+    else return {a.x * c + a.y * s, a.y * c - a.x * s};
+  }
+}
+
+// ---- in-register DFTs, natural order in and out, on a[o + i*st] ----------
+
+template <bool INV, typename T>
+__host__ __device__ __forceinline__ void dft2(cx<T>& a, cx<T>& b) {
+  const cx<T> t = a;
+  a = t + b;
+  b = t - b;
+}
+
+template <bool INV, typename T>
+__host__ __device__ __forceinline__ void dft4(cx<T>& a0, cx<T>& a1, cx<T>& a2, cx<T>& a3) {
+  const cx<T> t0 = a0 + a2, t1 = a0 - a2, t2 = a1 + a3, t3 = rot4<INV>(a1 - a3);
+  a0 = t0 + t2;
+  a2 = t0 - t2;
+  a1 = t1 + t3;
+  a3 = t1 - t3;
+}
+
+// DFT-3 (natural order): X0 = a+b+c, X1,2 = a - (b+c)/2 -+ i (sqrt3/2)(b-c)
+template <bool INV, typename T>
+__host__ __device__ __forceinline__ void dft3(cx<T>& a0, cx<T>& a1, cx<T>& a2) {
+  const T s3 = T(0.86602540378443864676);
+  const cx<T> s = a1 + a2, d = a1 - a2;
+  const cx<T> m = {a0.x - T(0.5) * s.x, a0.y - T(0.5) * s.y};
+  // forward: X1 = m - i s3 d, X2 = m + i s3 d
+  const cx<T> id = INV ? cx<T>{-s3 * d.y, s3 * d.x} : cx<T>{s3 * d.y, -s3 * d.x};
+  a0 = a0 + s;
+  a1 = m + id;
+  a2 = m - id;
+}
+
+// DFT-5 (natural order), Winograd-style with the real/imaginary constants of
+// w5 = e^{-2 pi i/5}.
+template <bool INV, typename T>
+__host__ __device__ __forceinline__ void dft5(cx<T>& a0, cx<T>& a1, cx<T>& a2, cx<T>& a3, cx<T>& a4) {
+  const T c1 = T(0.30901699437494742410);    // cos(2pi/5)
+  const T c2 = T(-0.80901699437494742410);   // cos(4pi/5)
+  const T s1 = T(0.95105651629515357212);    // sin(2pi/5)
+  const T s2 = T(0.58778525229247312917);    // sin(4pi/5)
+  const cx<T> b1 = a1 + a4, b4 = a1 - a4, b2 = a2 + a3, b3 = a2 - a3;
+  const cx<T> m1 = {a0.x + c1 * b1.x + c2 * b2.x, a0.y + c1 * b1.y + c2 * b2.y};
+  const cx<T> m2 = {a0.x + c2 * b1.x + c1 * b2.x, a0.y + c2 * b1.y + c1 * b2.y};
+  // n1 = s1 b4 + s2 b3 ; n2 = s2 b4 - s1 b3
+  const cx<T> n1 = {s1 * b4.x + s2 * b3.x, s1 * b4.y + s2 * b3.y};
+  const cx<T> n2 = {s2 * b4.x - s1 * b3.x, s2 * b4.y - s1 * b3.y};
+  // forward: X1 = m1 - i n1, X4 = m1 + i n1, X2 = m2 - i n2, X3 = m2 + i n2
+  const cx<T> in1 = INV ? cx<T>{-n1.y, n1.x} : cx<T>{n1.y, -n1.x};
+  const cx<T> in2 = INV ? cx<T>{-n2.y, n2.x} : cx<T>{n2.y, -n2.x};
+  a0 = a0 + b1 + b2;
+  a1 = m1 + in1;
+  a4 = m1 - in1;
+  a2 = m2 + in2;
+  a3 = m2 - in2;
+}
+
+template <bool INV, typename T>
+__host__ __device__ __forceinline__ void dft8(cx<T> (&a)[8]) {
+  // radix-2 DIT split: X[k] = E[k] + w8^k O[k], X[k+4] = E[k] - w8^k O[k]
+  cx<T> e0 = a[0], e1 = a[2], e2 = a[4], e3 = a[6];
+  cx<T> o0 = a[1], o1 = a[3], o2 = a[5], o3 = a[7];
+  dft4<INV>(e0, e1, e2, e3);
+  dft4<INV>(o0, o1, o2, o3);
+  o1 = rot16<INV, 2>(o1);
+  o2 = rot16<INV, 4>(o2);
+  o3 = rot16<INV, 6>(o3);
+  a[0] = e0 + o0; a[4] = e0 - o0;
+  a[1] = e1 + o1; a[5] = e1 - o1;
+  a[2] = e2 + o2; a[6] = e2 - o2;
+  a[3] = e3 + o3; a[7] = e3 - o3;
+}
+
+template <bool INV, typename T>
+__host__ __device__ __forceinline__ void dft16(cx<T> (&a)[16]) {
+  // 4 x 4: n = 4 n1 + n2, k = k1 + 4 k2
+  cx<T> b[16];  // b[4*k1 + n2]
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) {
+    cx<T> x0 = a[n2], x1 = a[4 + n2], x2 = a[8 + n2], x3 = a[12 + n2];
+    dft4<INV>(x0, x1, x2, x3);
+    b[0 + n2] = x0;
+    b[4 + n2] = x1;
+    b[8 + n2] = x2;
+    b[12 + n2] = x3;
+  }
+  // twiddles w16^{n2 k1}
+  b[4 + 1] = rot16<INV, 1>(b[4 + 1]);
+  b[4 + 2] = rot16<INV, 2>(b[4 + 2]);
+  b[4 + 3] = rot16<INV, 3>(b[4 + 3]);
+  b[8 + 1] = rot16<INV, 2>(b[8 + 1]);
+  b[8 + 2] = rot16<INV, 4>(b[8 + 2]);
+  b[8 + 3] = rot16<INV, 6>(b[8 + 3]);
+  b[12 + 1] = rot16<INV, 3>(b[12 + 1]);
+  b[12 + 2] = rot16<INV, 6>(b[12 + 2]);
+  b[12 + 3] = rot16<INV, 9>(b[12 + 3]);
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    cx<T> x0 = b[4 * k1 + 0], x1 = b[4 * k1 + 1], x2 = b[4 * k1 + 2], x3 = b[4 * k1 + 3];
+    dft4<INV>(x0, x1, x2, x3);
+    a[k1 + 0] = x0;
+    a[k1 + 4] = x1;
+    a[k1 + 8] = x2;
+    a[k1 + 12] = x3;
+  }
+}
+
+template <int R, bool INV, typename T>
+__host__ __device__ __forceinline__ void dft(cx<T> (&a)[R]) {
+  if constexpr (R == 1) {
+  } else if constexpr (R == 2) {
+    dft2<INV>(a[0], a[1]);
+  } else if constexpr (R == 3) {
+    dft3<INV>(a[0], a[1], a[2]);
+  } else if constexpr (R == 4) {
+    dft4<INV>(a[0], a[1], a[2], a[3]);
+  } else if constexpr (R == 5) {
+    dft5<INV>(a[0], a[1], a[2], a[3], a[4]);
+  } else if constexpr (R == 8) {
+    dft8<INV>(a);
+  } else if constexpr (R == 16) {
+    dft16<INV>(a);
+  } else {
+    static_assert(R == 16, "unsupported radix");
+  }
+}
+
+// ---- stage plan -----------------------------------------------------------
+
+struct Stages {
+  int n;
+  int r[12];
+};
+
+// Radices for length M with E values per thread: each radix divides E; the
+// largest admissible power of two first, then 3s and 5s.
+__host__ __device__ constexpr Stages make_stages(int M, int E) {
+  Stages s{0, {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0}};
+  int rem = M;
+  // powers of two
+  while (rem % 2 == 0) {
+    int r = 1;
+    while (r * 2 <= E && E % (r * 2) == 0 && rem % (r * 2) == 0 && r * 2 <= 16) r *= 2;
+    s.r[s.n++] = r;
+    rem /= r;
+  }
+  while (rem % 5 == 0) {
+    s.r[s.n++] = 5;
+    rem /= 5;
+  }
+  while (rem % 3 == 0) {
+    s.r[s.n++] = 3;
+    rem /= 3;
+  }
+  if (rem != 1) s.n = -1;  // not 5-smooth
+  return s;
+}
+
+__host__ __device__ constexpr bool stages_ok(int M, int E) {
+  Stages s = make_stages(M, E);
+  if (s.n <= 0 || M % E != 0) return false;
+  for (int i = 0; i < s.n; ++i)
+    if (E % s.r[i] != 0) return false;
+  return true;
+}
+
+__host__ __device__ constexpr int stage_L(int M, int E, int S) {
+  Stages s = make_stages(M, E);
+  int L = 1;
+  for (int i = 0; i < S; ++i) L *= s.r[i];
+  return L;
+}
+
+__host__ __device__ constexpr int stage_twoff(int M, int E, int S) {
+  Stages s = make_stages(M, E);
+  int off = 0, L = 1;
+  for (int i = 0; i < S; ++i) {
+    off += (s.r[i] - 1) * L;
+    L *= s.r[i];
+  }
+  return off;
+}
+
+// LDS index with one pad slot per 16 elements (breaks power-of-two strides).
+__device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
+__host__ __device__ constexpr int lds_len(int M) { return M + M / 16 + 4; }
+
+// One Stockham stage S and the exchange to stage S+1 (recursively).
+template <typename T, int M, int E, bool INV, int S>
+__device__ __forceinline__ void fft_stages(cx<T> (&v)[E], cx<T>* __restrict__ sh,
+                                           const cx<T>* __restrict__ tw, int t) {
+  constexpr Stages st = make_stages(M, E);
+  static_assert(st.n > 0, "length not 5-smooth");
+  constexpr int R = st.r[S];
+  constexpr int L = stage_L(M, E, S);
+  constexpr int TPT = M / E;
+  constexpr int NB = E / R;
+  constexpr int OFF = stage_twoff(M, E, S);
+  constexpr bool LAST = (S + 1 == st.n);
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const int b = t + q * TPT;
+    const int k = b % L;
+    cx<T> a[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) a[r] = v[q + r * NB];
+    if constexpr (S > 0) {
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        const cx<T> w = tw[OFF + (r - 1) * L + k];
+        a[r] = INV ? cmulc(a[r], w) : cmul(a[r], w);
+      }
+    }
+    dft<R, INV>(a);
+    if constexpr (LAST) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q + r * NB] = a[r];
+    } else {
+      const int base = (b / L) * L * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) sh[lpad(base + r * L)] = a[r];
+    }
+  }
+  if constexpr (!LAST) {
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < E; ++j) v[j] = sh[lpad(t + j * TPT)];
+    __syncthreads();
+    fft_stages<T, M, E, INV, S + 1>(v, sh, tw, t);
+  }
+}
+
+// Full transform of the thread's E registers (strided layout in and out).
+// Every thread of the block must call it (it contains block barriers).
+template <typename T, int M, int E, bool INV>
+__device__ __forceinline__ void fft(cx<T> (&v)[E], cx<T>* __restrict__ sh,
+                                    const cx<T>* __restrict__ tw, int t) {
+  fft_stages<T, M, E, INV, 0>(v, sh, tw, t);
+}
+
+}  // namespace tbs

@@ -1,0 +1,86 @@
+// Internal interfaces between the host runtime and the device passes.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace tbs {
+
+// Row pass: one FFT line per grid row (x axis).  Spectral layout of the
+// intermediate X: [rhs][M/CB][nrows][CB], CB = kBlock columns per block, rows
+// ordered rho = y*nz + z (3D) / rho = y (2D).  Spatial arrays (source, p, c,
+// V, pairing, gradient) are [rhs][z][y][x] / [z][y][x].
+enum RowIn { ROW_IN_SOURCE = 0, ROW_IN_SPECTRAL = 1 };
+enum RowAcc { ACC_NONE = 0, ACC_INIT = 1, ACC_ADD = 2, ACC_PAIR = 3 };
+
+// Spectral columns per contiguous block (cb) is 4, or 2 for FP64 plans with
+// 4096+ long columns (see spectral_block).
+
+struct RowArgs {
+  void* X;              // spectral intermediate (in and/or out)
+  const void* src;      // ROW_IN_SOURCE: source [rhs][P]
+  const void* V;        // potential [P] (OUT) ; nullptr = multiply by 0
+  void* p;              // accumulator [rhs][P]
+  void* pstore;         // optional copy of the updated accumulator [rhs][P]
+  void* c;              // Kahan compensation [rhs][P] (FP32 only)
+  const void* pair;     // ACC_PAIR: partial sums P_{L-1-m} [rhs][P]
+  void* grad;           // ACC_PAIR: g_V accumulator [rhs][P]
+  double* partials;     // [rhs][nblk] x 2 (|u|^2, |p|^2) for this term
+  const void* tw;       // twiddles for M
+  int nx, ny, nz;       // physical grid (nz = 1 in 2D)
+  int nrows;            // ny * nz
+  int nrhs;
+  int in_mode, acc, out_spec, conj_v;
+  int cb;
+  int xcd_remap;
+};
+
+struct ColArgs {
+  const void* in;
+  void* out;
+  const void* tw;
+  const void* ghat;     // CONV: folded spectrum
+  int op;               // COL_CONV / COL_FWD / COL_INV / COL_FULL
+  int conj_g;
+  int n_in, n_out;      // valid input length (zero above), stored outputs
+  int64_t in_astride, out_astride;
+  int64_t in_rs, in_s1, in_s0, out_rs, out_s1, out_s0;
+  int nrhs, n1, n0;
+  int cb;               // spectral block width of the layout
+  int zcols, zlim;      // column validity: i0*zcols + col/cb < zlim
+  int mx, mm;           // fold sizes of kx (= i1*cb + col%cb) and kmid (= i0)
+  int64_t g_sx, g_sm;   // table strides for fold(kx), fold(kmid)
+  int xcd_remap;
+};
+enum ColOp { COL_CONV = 0, COL_FWD = 1, COL_INV = 2, COL_FULL = 3 };
+
+// Lengths the library has kernels for.
+bool fft_length_supported(int M);
+int fft_elems_per_thread(int M);
+int row_rows_per_block(int M, bool fp64);
+int spectral_block(int My, bool fp64);
+int col_max_cols(int M, bool fp64);  // widest column block that fits LDS
+// Launchers (return hipError_t as int).
+int launch_row_pass(bool fp64, int M, const RowArgs& a, int nblk_rows, hipStream_t s);
+int launch_col_pass(bool fp64, int M, int NC, const ColArgs& a, hipStream_t s);
+int launch_row_fft_full(int M, void* data, const void* tw, int nrows, int inverse, hipStream_t s);
+
+// Elementwise / reduction kernels.
+int launch_finish_norms(const double* partials, int nterms, int nvalid, int nrhs, int nblk,
+                        double* resid, hipStream_t s);
+int launch_green_eval(void* W, int ndim, const int64_t* M, double dx, double k0r, double k0i,
+                      double w0r, double w0i, hipStream_t s);
+int launch_green_fold(const void* What, void* ghat, bool fp64, int ndim, const int64_t* M,
+                      hipStream_t s);
+int launch_potential(const double* c, void* V, void* dVdc, bool fp64, int64_t n, double omega,
+                     double a_abs, double disp, double k0sq_r, double k0sq_i, hipStream_t s);
+int launch_harmonic_source(const void* p1, const double* c, void* S2, bool fp64, int64_t n,
+                           int nrhs, double coef, hipStream_t s);
+int launch_misfit(const void* p, const int64_t* rec, const void* p_obs, void* q, double* jpart,
+                  bool fp64, int64_t P, int nrec, int nrhs, hipStream_t s);
+int launch_grad_assemble(const void* g, int nrhs, const void* dVdc, double* grad_c, bool fp64,
+                         int64_t P, int accumulate, hipStream_t s);
+int launch_zero(void* p, int64_t bytes, hipStream_t s);
+int launch_sum_half(const double* parts, int n, double* out, hipStream_t s);
+
+}  // namespace tbs

@@ -1,0 +1,402 @@
+// Streaming passes of the zero-padded Green's-function convolution
+// u_{n+1} = G (V u_n), G = F^-1 diag(G^) F (paper Sec. 2.2, Eqs. TBS_1 and
+// TBS_algorithm), as HBM-streaming CDNA4 kernels.
+//
+//  * k_row_pass: one x line per grid row.  Inverse x-FFT of the previous term's
+//    spectral row, crop to the physical row (term u_{n-1}), Kahan (FP32) or
+//    plain (FP64) p += u, FP64 norm partials, w = V u (conj(V) u for the
+//    adjoint, or the pairing sum g += conj(u) P for the gradient), zero-pad,
+//    forward x-FFT, store.  The first pass reads the source instead.
+//  * k_col_pass: one strided line (y in 2D, y or z in 3D) per column: zero-pad,
+//    forward FFT, multiply by the folded spectrum G^ (conj for the adjoint),
+//    inverse FFT, crop; or only the forward / inverse half of that.
+//
+// Every FFT line lives in registers of one thread group (see tbs_fft.hpp);
+// LDS is used only for the exchanges between radix stages.  Lines are read
+// and written in contiguous kBlock-wide column blocks so that every HBM access
+// is a full, coalesced segment.
+#include "tbs_fft.hpp"
+#include "tbs_internal.hpp"
+
+namespace tbs {
+
+__device__ __forceinline__ void kahan_add(float& s, float& c, float x) {
+#pragma clang fp contract(off)
+  const float y = x - c;
+  const float t = s + y;
+  c = (t - s) - y;
+  s = t;
+}
+
+// Workgroups are dealt round-robin to the 8 XCDs; give each XCD a contiguous
+// range of logical blocks so that neighbours (which share table rows / V rows
+// through L2) run on the same XCD.
+__device__ __forceinline__ int xcd_block(int bid, int nblk, int on) {
+  constexpr int kXcd = 8;
+  if (!on || (nblk % kXcd) != 0) return bid;
+  return (bid % kXcd) * (nblk / kXcd) + bid / kXcd;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ double norm2(cx<T> a) {
+  return (double)a.x * (double)a.x + (double)a.y * (double)a.y;
+}
+
+__device__ __forceinline__ int fold(int k, int m) { return k <= (m >> 1) ? k : m - k; }
+
+// ---------------------------------------------------------------- row pass --
+
+template <typename T, int M, int E, int NR, int CB>
+__global__ void __launch_bounds__(NR * (M / E)) k_row_pass(RowArgs a) {
+  constexpr int TPT = M / E;
+  constexpr int NKB = M / CB;
+  constexpr int LD = lds_len(M);
+  constexpr int NT = NR * TPT;
+  constexpr int NW = (NT + 63) / 64;
+  static_assert(TPT % CB == 0, "line too short for the column block");
+  static_assert(E % 2 == 0, "E must be even");
+  __shared__ cx<T> sh[NR * LD];
+  __shared__ double red[2 * NW];
+
+  const int tid = threadIdx.x;
+  const int tlo = tid % CB;
+  const int r = (tid / CB) % NR;
+  const int thi = tid / (CB * NR);
+  const int t = thi * CB + tlo;
+  const int lb = xcd_block(blockIdx.x, gridDim.x, a.xcd_remap);
+  const int rhs = lb % a.nrhs;
+  const int rb = lb / a.nrhs;
+  const int nblk = (a.nrows + NR - 1) / NR;
+  const int row = rb * NR + r;
+  const bool valid = row < a.nrows;
+  cx<T>* shr = sh + r * LD;
+  const cx<T>* tw = (const cx<T>*)a.tw;
+  cx<T>* X = (cx<T>*)a.X;
+  const int64_t P = (int64_t)a.nrows * a.nx;
+  const int yy = valid ? row / a.nz : 0;
+  const int zz = valid ? row % a.nz : 0;
+  const int64_t srow = (int64_t)(zz * a.ny + yy) * a.nx;  // spatial offset of this row
+  const int64_t sp_base = (int64_t)rhs * P + srow;
+  const int64_t xbase = ((int64_t)rhs * NKB * a.nrows + (valid ? row : 0)) * CB;
+  const int64_t kbstride = (int64_t)a.nrows * CB;
+
+  cx<T> v[E];
+  double su = 0.0, sp = 0.0;
+  if (a.in_mode == ROW_IN_SPECTRAL) {
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int kx = t + j * TPT;
+      v[j] = valid ? X[xbase + (int64_t)(kx / CB) * kbstride + (kx % CB)] : cx<T>{T(0), T(0)};
+    }
+    fft<T, M, E, true>(v, shr, tw, t);
+    cx<T>* p = (cx<T>*)a.p;
+    const cx<T>* Vp = (const cx<T>*)a.V;
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int x = t + j * TPT;
+      cx<T> w = {T(0), T(0)};
+      if (j < E / 2 && valid && x < a.nx) {
+        const int64_t i = sp_base + x;
+        const cx<T> u = v[j];
+        if (a.acc == ACC_INIT) {
+          p[i] = u;
+          if (a.pstore) ((cx<T>*)a.pstore)[i] = u;
+          if constexpr (sizeof(T) == 4) ((cx<T>*)a.c)[i] = cx<T>{T(0), T(0)};
+          const double n = norm2(u);
+          su += n;
+          sp += n;
+        } else if (a.acc == ACC_ADD) {
+          cx<T> pp = p[i];
+          if constexpr (sizeof(T) == 4) {
+            cx<T>* cc = (cx<T>*)a.c;
+            cx<T> ci = cc[i];
+            kahan_add(pp.x, ci.x, u.x);
+            kahan_add(pp.y, ci.y, u.y);
+            cc[i] = ci;
+          } else {
+            pp = pp + u;
+          }
+          p[i] = pp;
+          if (a.pstore) ((cx<T>*)a.pstore)[i] = pp;
+          su += norm2(u);
+          sp += norm2(pp);
+        } else if (a.acc == ACC_PAIR) {
+          cx<T>* g = (cx<T>*)a.grad;
+          const cx<T> pr = ((const cx<T>*)a.pair)[i];
+          g[i] = g[i] + cmulc(pr, u);   // conj(u) * P
+          su += norm2(u);
+        }
+        if (a.out_spec && Vp != nullptr) {
+          const cx<T> vv = Vp[srow + x];
+          w = a.conj_v ? cmulc(u, vv) : cmul(u, vv);
+        }
+      }
+      v[j] = w;
+    }
+  } else {
+    const cx<T>* src = (const cx<T>*)a.src;
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int x = t + j * TPT;
+      v[j] = (j < E / 2 && valid && x < a.nx) ? src[sp_base + x] : cx<T>{T(0), T(0)};
+    }
+  }
+
+  if (a.acc != ACC_NONE) {
+    su = wave_sum(su);
+    sp = wave_sum(sp);
+    const int wv = tid >> 6;
+    if ((tid & 63) == 0) {
+      red[2 * wv] = su;
+      red[2 * wv + 1] = sp;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      // every thread of the block works on rows of the same rhs
+      double a0 = 0.0, a1 = 0.0;
+      for (int k = 0; k < NW; ++k) {
+        a0 += red[2 * k];
+        a1 += red[2 * k + 1];
+      }
+      a.partials[2 * ((int64_t)rhs * nblk + rb)] = a0;
+      a.partials[2 * ((int64_t)rhs * nblk + rb) + 1] = a1;
+    }
+  }
+
+  if (a.out_spec) {
+    fft<T, M, E, false>(v, shr, tw, t);
+    if (valid) {
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        const int kx = t + j * TPT;
+        X[xbase + (int64_t)(kx / CB) * kbstride + (kx % CB)] = v[j];
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------- column pass --
+
+template <typename T, int M, int E, int NC, int OP>
+__global__ void __launch_bounds__(NC * (M / E)) k_col_pass(ColArgs a) {
+  constexpr int TPT = M / E;
+  constexpr int LD = lds_len(M);
+  constexpr bool HALF_IN = (OP == COL_CONV || OP == COL_FWD);
+  constexpr bool HALF_OUT = (OP == COL_CONV || OP == COL_INV);
+  __shared__ cx<T> sh[NC * LD];
+
+  const int tid = threadIdx.x;
+  const int col = tid % NC;
+  const int tt = tid / NC;
+  const int lb = xcd_block(blockIdx.x, gridDim.x, a.xcd_remap);
+  const int rhs = lb % a.nrhs;
+  const int rest = lb / a.nrhs;
+  const int i0 = rest % a.n0;
+  const int i1 = rest / a.n0;
+  const bool cvalid = (i0 * a.zcols + col / a.cb) < a.zlim;
+  cx<T>* shc = sh + col * LD;
+  const cx<T>* tw = (const cx<T>*)a.tw;
+  const cx<T>* in = (const cx<T>*)a.in;
+  cx<T>* out = (cx<T>*)a.out;
+  const int64_t ib = rhs * a.in_rs + i1 * a.in_s1 + i0 * a.in_s0 + col;
+  const int64_t ob = rhs * a.out_rs + i1 * a.out_s1 + i0 * a.out_s0 + col;
+
+  cx<T> v[E];
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const int pos = tt + j * TPT;
+    const bool ld = (!HALF_IN || j < E / 2) && cvalid && pos < a.n_in;
+    v[j] = ld ? in[ib + pos * a.in_astride] : cx<T>{T(0), T(0)};
+  }
+  if constexpr (OP != COL_INV) fft<T, M, E, false>(v, shc, tw, tt);
+  if constexpr (OP == COL_CONV) {
+    const cx<T>* g = (const cx<T>*)a.ghat;
+    const int kx = i1 * a.cb + (col % a.cb);
+    const int64_t gb = fold(kx, a.mx) * a.g_sx + fold(i0, a.mm) * a.g_sm;
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const cx<T> gv = g[gb + fold(tt + j * TPT, M)];
+      v[j] = a.conj_g ? cmulc(v[j], gv) : cmul(v[j], gv);
+    }
+  }
+  if constexpr (OP == COL_CONV || OP == COL_INV) fft<T, M, E, true>(v, shc, tw, tt);
+  if (cvalid) {
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int pos = tt + j * TPT;
+      if ((!HALF_OUT || j < E / 2) && pos < a.n_out) out[ob + pos * a.out_astride] = v[j];
+    }
+  }
+}
+
+// Plain in-place FFT of contiguous rows [nrows][M] (tabulation, FP64).
+template <typename T, int M, int E, int NR>
+__global__ void __launch_bounds__(NR * (M / E)) k_row_fft_full(cx<T>* data, const cx<T>* tw,
+                                                               int nrows, int inverse) {
+  constexpr int TPT = M / E;
+  constexpr int LD = lds_len(M);
+  __shared__ cx<T> sh[NR * LD];
+  const int tid = threadIdx.x;
+  const int r = tid / TPT;
+  const int t = tid % TPT;
+  const int row = blockIdx.x * NR + r;
+  const bool valid = row < nrows;
+  cx<T>* d = data + (int64_t)(valid ? row : 0) * M;
+  cx<T> v[E];
+#pragma unroll
+  for (int j = 0; j < E; ++j) v[j] = valid ? d[t + j * TPT] : cx<T>{T(0), T(0)};
+  if (inverse)
+    fft<T, M, E, true>(v, sh + r * LD, tw, t);
+  else
+    fft<T, M, E, false>(v, sh + r * LD, tw, t);
+  if (valid) {
+#pragma unroll
+    for (int j = 0; j < E; ++j) d[t + j * TPT] = v[j];
+  }
+}
+
+// ----------------------------------------------------------- dispatching --
+
+// Lengths with compiled kernels (powers of two; every one is 5-smooth).
+#define TBS_FOR_EACH_LENGTH(X) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)
+
+bool fft_length_supported(int M) {
+  switch (M) {
+#define TBS_CASE(m) case m:
+    TBS_FOR_EACH_LENGTH(TBS_CASE)
+#undef TBS_CASE
+    return true;
+    default:
+      return false;
+  }
+}
+
+constexpr int elems_per_thread(int M) { return M <= 64 ? 4 : (M <= 512 ? 8 : 16); }
+int fft_elems_per_thread(int M) { return elems_per_thread(M); }
+
+// Rows per row-pass block: LDS (160 KB per CU) holds NR lines of M values.
+constexpr int rows_per_block(int M, bool fp64) {
+  return fp64 ? (M >= 4096 ? 2 : 4) : 4;
+}
+int row_rows_per_block(int M, bool fp64) { return rows_per_block(M, fp64); }
+
+// Contiguous spectral columns per block of the intermediate layout: 4, except
+// FP64 with columns of 4096+ values, where 4 lines would not fit in LDS.
+int spectral_block(int My, bool fp64) { return (fp64 && My >= 4096) ? 2 : 4; }
+
+template <typename T, int M>
+static int row_launch(const RowArgs& a, int nblk_rows, hipStream_t s) {
+  constexpr int E = elems_per_thread(M);
+  constexpr int NR = rows_per_block(M, sizeof(T) == 8);
+  const int grid = nblk_rows * a.nrhs;
+  if (a.cb == 4) {
+    hipLaunchKernelGGL((k_row_pass<T, M, E, NR, 4>), dim3(grid), dim3(NR * (M / E)), 0, s, a);
+  } else if (a.cb == 2) {
+    hipLaunchKernelGGL((k_row_pass<T, M, E, NR, 2>), dim3(grid), dim3(NR * (M / E)), 0, s, a);
+  } else {
+    return (int)hipErrorInvalidValue;
+  }
+  return (int)hipGetLastError();
+}
+
+int launch_row_pass(bool fp64, int M, const RowArgs& a, int nblk_rows, hipStream_t s) {
+  switch (M) {
+#define TBS_CASE(m) \
+  case m:           \
+    return fp64 ? row_launch<double, m>(a, nblk_rows, s) : row_launch<float, m>(a, nblk_rows, s);
+    TBS_FOR_EACH_LENGTH(TBS_CASE)
+#undef TBS_CASE
+    default:
+      return (int)hipErrorInvalidValue;
+  }
+}
+
+template <typename T, int M, int NC>
+static int col_launch(const ColArgs& a, hipStream_t s) {
+  constexpr int E = elems_per_thread(M);
+  const int grid = a.nrhs * a.n1 * a.n0;
+  const dim3 blk(NC * (M / E));
+  switch (a.op) {
+    case COL_CONV:
+      hipLaunchKernelGGL((k_col_pass<T, M, E, NC, COL_CONV>), dim3(grid), blk, 0, s, a);
+      break;
+    case COL_FWD:
+      hipLaunchKernelGGL((k_col_pass<T, M, E, NC, COL_FWD>), dim3(grid), blk, 0, s, a);
+      break;
+    case COL_INV:
+      hipLaunchKernelGGL((k_col_pass<T, M, E, NC, COL_INV>), dim3(grid), blk, 0, s, a);
+      break;
+    default:
+      if constexpr (sizeof(T) == 8) {
+        hipLaunchKernelGGL((k_col_pass<T, M, E, NC, COL_FULL>), dim3(grid), blk, 0, s, a);
+      } else {
+        return (int)hipErrorInvalidValue;
+      }
+  }
+  return (int)hipGetLastError();
+}
+
+constexpr bool col_fits(int M, int NC, int esz) {
+  return (long)NC * lds_len(M) * esz <= 160L * 1024;
+}
+int col_max_cols(int M, bool fp64) {
+  const int esz = fp64 ? 16 : 8;
+  return col_fits(M, 4, esz) ? 4 : (col_fits(M, 2, esz) ? 2 : 1);
+}
+
+template <typename T, int M>
+static int col_launch_nc(int NC, const ColArgs& a, hipStream_t s) {
+  constexpr int esz = (int)sizeof(cx<T>);
+  if constexpr (col_fits(M, 4, esz)) {
+    if (NC == 4) return col_launch<T, M, 4>(a, s);
+  }
+  if constexpr (col_fits(M, 2, esz)) {
+    if (NC == 2) return col_launch<T, M, 2>(a, s);
+  }
+  if constexpr (M <= 512 && col_fits(M, 16, esz)) {
+    if (NC == 16) return col_launch<T, M, 16>(a, s);
+  }
+  return (int)hipErrorInvalidValue;
+}
+
+int launch_col_pass(bool fp64, int M, int NC, const ColArgs& a, hipStream_t s) {
+  switch (M) {
+#define TBS_CASE(m) \
+  case m:           \
+    return fp64 ? col_launch_nc<double, m>(NC, a, s) : col_launch_nc<float, m>(NC, a, s);
+    TBS_FOR_EACH_LENGTH(TBS_CASE)
+#undef TBS_CASE
+    default:
+      return (int)hipErrorInvalidValue;
+  }
+}
+
+template <int M>
+static int rowfull_launch(void* data, const void* tw, int nrows, int inverse, hipStream_t s) {
+  constexpr int E = elems_per_thread(M);
+  constexpr int NR = rows_per_block(M, true);
+  hipLaunchKernelGGL((k_row_fft_full<double, M, E, NR>), dim3((nrows + NR - 1) / NR),
+                     dim3(NR * (M / E)), 0, s, (cx<double>*)data, (const cx<double>*)tw, nrows,
+                     inverse);
+  return (int)hipGetLastError();
+}
+
+int launch_row_fft_full(int M, void* data, const void* tw, int nrows, int inverse, hipStream_t s) {
+  switch (M) {
+#define TBS_CASE(m) \
+  case m:           \
+    return rowfull_launch<m>(data, tw, nrows, inverse, s);
+    TBS_FOR_EACH_LENGTH(TBS_CASE)
+#undef TBS_CASE
+    default:
+      return (int)hipErrorInvalidValue;
+  }
+}
+
+}  // namespace tbs

@@ -1,0 +1,42 @@
+"""CPU checks of the device FFT building blocks compiled as host code: the
+radix-2/3/4/5/8/16 butterflies and the radix plans of every compiled length."""
+import ctypes
+import os
+
+import numpy as np
+import pytest
+
+HC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                  "paper_2507_13754_amd", "_build", "libtbs_hostcheck.so")
+
+
+@pytest.fixture(scope="module")
+def hc():
+    if not os.path.exists(HC):
+        pytest.fail(f"{HC} missing: run __graft_entry__.build()")
+    return ctypes.CDLL(HC)
+
+
+@pytest.mark.parametrize("R", [2, 3, 4, 5, 8, 16])
+@pytest.mark.parametrize("inv", [0, 1])
+def test_radix_butterfly(hc, R, inv):
+    rng = np.random.default_rng(R + 10 * inv)
+    for _ in range(5):
+        x = rng.standard_normal(R) + 1j * rng.standard_normal(R)
+        inp = np.ascontiguousarray(np.stack([x.real, x.imag], 1).ravel())
+        out = np.zeros(2 * R)
+        assert hc.tbs_hostcheck_dft(R, inv, inp.ctypes.data_as(ctypes.c_void_p),
+                                    out.ctypes.data_as(ctypes.c_void_p)) == 0
+        y = out[0::2] + 1j * out[1::2]
+        ref = np.fft.ifft(x) * R if inv else np.fft.fft(x)
+        assert np.max(np.abs(y - ref)) < 1e-14 * np.max(np.abs(ref)) * R
+
+
+@pytest.mark.parametrize("M,E", [(16, 4), (32, 4), (64, 4), (128, 8), (256, 8), (512, 8),
+                                 (1024, 16), (2048, 16), (4096, 16), (2500, 20), (1000, 40)])
+def test_stage_plan(hc, M, E):
+    r = (ctypes.c_int * 12)()
+    n = hc.tbs_hostcheck_stages(M, E, r)
+    radices = [r[i] for i in range(n)]
+    assert n > 0 and int(np.prod(radices)) == M
+    assert all(E % x == 0 for x in radices)
