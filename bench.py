@@ -1,0 +1,280 @@
+#!/usr/bin/env python3
+"""Throughput of the Born-series hot path on one MI355X.
+
+One step = one full L-term solve (every row and column pass of every term)
+of one batch of right-hand sides, with inputs already resident in HBM.
+value = physical grid points x summed terms x RHS / step time
+(grid-point.terms/s), for the FP32 (Kahan) plan; the plain FP64 plan is timed
+beside it on the same input and its accuracy gap is stated.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
+METRIC = "Born grid-point·terms/s + HBM GB/s frac, FP32 batched vs FP64 plain, 1 GPU"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_sources_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("tbs_passes.hip", "tbs_fft.hpp", "tbs_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_2507_13754_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def pass_bytes(kind: str, ndim: int, N, M, B: int, esz: int, kahan: bool, ghat_bytes: int) -> int:
+    """Algorithmic HBM bytes of one launch of a pass: every array the pass
+    must read or write, once.  N, M: (x, y, z) physical / padded sizes."""
+    P = N[0] * N[1] * N[2]
+    rows = N[1] * N[2]
+    X = B * rows * M[0] * esz                 # x-spectral intermediate
+    acc_rw = B * P * esz * (4 if kahan else 2)   # p (and Kahan c) read + write
+    if kind == "row_first":
+        return B * P * esz + X
+    if kind == "row_mid":
+        return 2 * X + P * esz + acc_rw
+    if kind == "row_last":
+        return X + acc_rw
+    if kind == "col_conv":
+        if ndim == 2:
+            return 2 * X + ghat_bytes
+        return 2 * B * M[0] * M[1] * N[2] * esz + ghat_bytes
+    if kind in ("col_fwd", "col_inv"):
+        return X + B * M[0] * M[1] * N[2] * esz
+    raise ValueError(kind)
+
+
+def step_bytes(ndim, N, M, B, esz, kahan, ghat_bytes, L) -> int:
+    f = lambda k: pass_bytes(k, ndim, N, M, B, esz, kahan, ghat_bytes)  # noqa: E731
+    total = f("row_first") + (L - 1) * f("row_mid") + f("row_last") + L * f("col_conv")
+    if ndim == 3:
+        total += L * (f("col_fwd") + f("col_inv"))
+    return total
+
+
+def make_workload(name: str):
+    import workloads
+    if name == "absorb2d":
+        case = workloads.absorb2d()
+        desc = ("absorb2d: 2048x2048 grid, dx=lambda/6 at 5 MHz, 111 Gaussian blobs c0 +-3%, "
+                "0.75 dB/(MHz^1.5 cm) y=1.5 with dispersion, 64-element line array, 30 terms, 1 RHS")
+    elif name == "plain2d":
+        case = workloads.plain2d()
+        desc = "plain2d: 256x256, dx=lambda/8 at 1 MHz, 1% GRF, 0.5 dB/cm/MHz y=1, 32 elements, 16 terms"
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return case, desc
+
+
+def time_solves(plan, s, V, L, out, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        plan.solve(s, V, L, out=out)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        plan.solve(s, V, L, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / steps, wall / steps * 1e3
+
+
+def profile_passes(plan, s, V, L, out, steps):
+    import paper_2507_13754_amd as tbs
+    plan.profile(True)
+    for _ in range(steps):
+        plan.solve(s, V, L, out=out)
+    prof = plan.profile_read()
+    plan.profile(False)
+    return prof
+
+
+def cpu_baseline(case, budget_s: float):
+    """The FP64 oracle on the host: the same series on the same input for as
+    many terms as fit the time budget (spectrum tabulation excluded)."""
+    import oracle
+    k0 = oracle.background_k0(case.omega, case.c0, case.alpha0, case.y)
+    V = oracle.potential(case.c, case.omega, case.c0, case.alpha0, case.y)
+    G = oracle.GreenOperator(k0, case.dx, case.grid)
+    t0 = time.perf_counter()
+    G(case.sources)
+    t_apply = time.perf_counter() - t0
+    nterms = int(max(1, min(case.nterms, budget_s // max(t_apply, 1e-3))))
+    t0 = time.perf_counter()
+    oracle.born_series(G, case.sources, V, nterms)
+    t = time.perf_counter() - t0
+    gpt = case.points * nterms * case.sources.shape[0]
+    return {
+        "value": gpt / t,
+        "unit": "grid-point·terms/s",
+        "cores": int(oracle.tbs_oracle.WORKERS),
+        "kind": "oracle",
+        "sample": f"{case.name}: first {nterms} of {case.nterms} terms, {case.sources.shape[0]} RHS, "
+                  f"FP64 numpy/scipy.fft, {t:.1f} s",
+    }
+
+
+def read_counters(workload: str, kernel: str):
+    path = os.path.join(ROOT, "profiles", f"counters_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    if d.get("sources_sha256_16") != kernel_sources_hash():
+        return None
+    return d.get("traffic_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="absorb2d", choices=["absorb2d", "plain2d"])
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain 256 MiB device copy (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        log("bench.py measures one GPU: this build runs the hot path on a single MI355X "
+            "(frequencies/sources would shard across GPUs with no communication); use --gpus 1")
+        sys.exit(2)
+
+    import torch
+    import paper_2507_13754_amd as tbs
+
+    dev = torch.device("cuda:0")
+    log(f"[bench] building workload {args.workload}")
+    case, desc = make_workload(args.workload)
+    L = case.nterms
+    B = case.sources.shape[0]
+    k0 = tbs.background_k0(case.omega, case.c0, case.alpha0, case.y)
+    c_dev = torch.from_numpy(case.c).to(dev)
+
+    res = {}
+    for name, dtype in (("c64", torch.complex64), ("c128", torch.complex128)):
+        if name == "c128" and args.no_fp64:
+            continue
+        log(f"[bench] {name}: plan + tabulation")
+        t0 = time.perf_counter()
+        plan = tbs.Plan(case.grid, case.dx, k0, dtype=dtype, batch=B).tabulate()
+        t_tab = time.perf_counter() - t0
+        V = plan.potential(c_dev, case.omega, case.c0, case.alpha0, case.y)
+        s = torch.from_numpy(case.sources).to(dev, dtype)
+        out = torch.empty((B,) + case.grid, dtype=dtype, device=dev)
+        steps = args.steps if name == "c64" else max(3, args.steps // 2)
+        ms_ev, ms_wall = time_solves(plan, s, V, L, out, steps, args.warmup)
+        log(f"[bench] {name}: {ms_ev:.3f} ms/step (events), {ms_wall:.3f} ms/step (wall)")
+        prof_steps = max(3, steps // 2)
+        prof = profile_passes(plan, s, V, L, out, prof_steps)
+        _, r = plan.solve(s, V, L, out=out, residual=True)
+        res[name] = dict(plan=plan, out=out.clone(), ms=ms_ev, ms_wall=ms_wall, prof=prof,
+                         t_tab=t_tab, steps=steps, prof_steps=prof_steps, resid=r)
+        if args.calib_copy and name == "c64":
+            a = torch.empty(256 * 1024 * 1024 // 4, dtype=torch.float32, device=dev).fill_(1.0)
+            bb = torch.empty_like(a)
+            for _ in range(3):
+                bb.copy_(a)
+            torch.cuda.synchronize()
+            log("[bench] calibration copy of 256 MiB done (3 launches)")
+
+    P = case.points
+    r32 = res["c64"]
+    plan32 = r32["plan"]
+    N = (case.grid[-1], case.grid[-2], case.grid[-3] if len(case.grid) == 3 else 1)
+    Mx, My, Mz = plan32.padded
+    M = (Mx, My, Mz)
+    ndim = len(case.grid)
+
+    def roofline(rr, esz, kahan):
+        ghat_bytes = (Mx // 2 + 1) * (My // 2 + 1) * ((Mz // 2 + 1) if ndim == 3 else 1) * esz
+        kinds = {k: v for k, v in rr["prof"].items() if v[1] > 0}
+        dom = max(kinds, key=lambda k: kinds[k][0])
+        avg_ms = kinds[dom][0] / kinds[dom][1]
+        nbytes = pass_bytes(dom, ndim, N, M, B, esz, kahan, ghat_bytes)
+        ach = nbytes / (avg_ms * 1e-3) / 1e9
+        passes = {k: {"avg_us": 1e3 * v[0] / v[1], "launches_per_step": v[1] / rr["prof_steps"],
+                      "alg_bytes": pass_bytes(k, ndim, N, M, B, esz, kahan, ghat_bytes),
+                      "GBps": pass_bytes(k, ndim, N, M, B, esz, kahan, ghat_bytes) / (v[0] / v[1] * 1e-3) / 1e9}
+                  for k, v in kinds.items()}
+        sb = step_bytes(ndim, N, M, B, esz, kahan, ghat_bytes, L)
+        return dom, nbytes, avg_ms, ach, passes, sb
+
+    dom, nbytes, avg_ms, ach, passes32, sb32 = roofline(r32, 8, True)
+    traffic = read_counters(args.workload, dom)
+    value = P * L * B / (r32["ms"] * 1e-3)
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "grid-point·terms/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r32["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": desc, "grid": list(case.grid), "padded": [Mx, My] + ([Mz] if ndim == 3 else []),
+                   "nterms": L, "rhs": B, "dx_m": case.dx, "freq_hz": case.freq,
+                   "plan_dtype": "complex64 + Kahan-compensated sum"},
+        "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": ach / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom,
+                     "alg_bytes_per_launch": nbytes, "avg_launch_ms": avg_ms},
+        "step_roofline": {"alg_bytes_per_step": sb32, "achieved_GBps": sb32 / (r32["ms"] * 1e-3) / 1e9,
+                          "frac": sb32 / (r32["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                          "bytes_per_gpt": sb32 / (P * L * B)},
+        "passes": passes32,
+        "ms_per_step_wall": r32["ms_wall"],
+        "tabulation_s": r32["t_tab"],
+        "residual_last": float(np.max(r32["resid"][:, -1])),
+    }
+    if "c128" in res:
+        r64 = res["c128"]
+        p32 = r32["out"].cpu().numpy().astype(np.complex128)
+        p64 = r64["out"].cpu().numpy()
+        err = max(float(np.linalg.norm(p32[b] - p64[b]) / np.linalg.norm(p64[b])) for b in range(B))
+        _, _, _, ach64, passes64, sb64 = roofline(r64, 16, False)
+        line["fp64_plain"] = {"value": P * L * B / (r64["ms"] * 1e-3), "ms_per_step": r64["ms"],
+                              "step_GBps": sb64 / (r64["ms"] * 1e-3) / 1e9,
+                              "step_frac": sb64 / (r64["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                              "passes": passes64}
+        line["speedup_fp32_vs_fp64"] = r64["ms"] / r32["ms"]
+        line["rel_l2_fp32_vs_fp64"] = err
+    if not args.no_cpu_baseline:
+        log(f"[bench] CPU oracle baseline (~{args.cpu_seconds:.0f} s)")
+        line["cpu_baseline"] = cpu_baseline(case, args.cpu_seconds)
+    for r in res.values():
+        r["plan"].close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -184,6 +184,19 @@ int tbs_misfit(tbs_plan *plan, const void *p_dev, const int64_t *rec_dev, int nr
 int tbs_speed_gradient(tbs_plan *plan, const void *g_dev, const void *dVdc_dev,
                        double *grad_c_dev, int accumulate);
 
+/* Per-pass device timing.  While enabled, every pass launch is bracketed by
+ * two HIP events recorded on the plan's stream.  Pass kinds (index into the
+ * output arrays): 0 first row pass (source in), 1 middle row passes,
+ * 2 last row pass, 3 column convolution passes, 4 column forward-only passes
+ * (3D y), 5 column inverse-only passes (3D y).  Enabling (again) resets the
+ * counters. */
+int tbs_profile_enable(tbs_plan *plan, int enable);
+
+/* Synchronise the plan's stream and return, per pass kind, the summed event
+ * time in ms (ms_out[6]) and the number of launches (count_out[6]); resets
+ * the counters. */
+int tbs_profile_read(tbs_plan *plan, double *ms_out, int64_t *count_out);
+
 /* Release the plan and all device memory it owns (NULL-safe).  Synchronises
  * the plan's stream first. */
 void tbs_plan_destroy(tbs_plan *plan);

@@ -44,7 +44,8 @@ import scipy.fft
 import scipy.linalg
 import scipy.special
 
-WORKERS = os.cpu_count() or 1
+# scipy.fft threads: the host's cores, at most 16 (one GPU's share of a box)
+WORKERS = max(1, min(os.cpu_count() or 1, 16))
 
 
 # ---------------------------------------------------------------- medium ----

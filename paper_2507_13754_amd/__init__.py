@@ -31,8 +31,10 @@ EXPORTS = (
     "tbs_background_k0", "tbs_hankel01", "tbs_self_cell", "tbs_plan_create", "tbs_plan_info",
     "tbs_plan_set_stream", "tbs_green_tabulate", "tbs_green_import", "tbs_green_export",
     "tbs_potential", "tbs_solve", "tbs_harmonic_source", "tbs_adjoint", "tbs_misfit",
-    "tbs_speed_gradient", "tbs_plan_destroy", "tbs_last_error",
+    "tbs_speed_gradient", "tbs_profile_enable", "tbs_profile_read", "tbs_plan_destroy",
+    "tbs_last_error",
 )
+PASS_KINDS = ("row_first", "row_mid", "row_last", "col_conv", "col_fwd", "col_inv")
 
 
 class TBSError(RuntimeError):
@@ -85,6 +87,8 @@ def library() -> ctypes.CDLL:
         "tbs_adjoint": (ctypes.c_int, [vp, vp, vp, ctypes.c_int, vp, vp, dp, ctypes.c_int]),
         "tbs_misfit": (ctypes.c_int, [vp, vp, vp, ctypes.c_int, vp, vp, vp]),
         "tbs_speed_gradient": (ctypes.c_int, [vp, vp, vp, vp, ctypes.c_int]),
+        "tbs_profile_enable": (ctypes.c_int, [vp, ctypes.c_int]),
+        "tbs_profile_read": (ctypes.c_int, [vp, dp, i64p]),
         "tbs_plan_destroy": (None, [vp]),
         "tbs_last_error": (ctypes.c_char_p, [vp]),
     }
@@ -324,6 +328,18 @@ class Plan:
         _check(library().tbs_misfit(self._h, pp, rp, nrec, op, ctypes.c_void_p(q.data_ptr()),
                                     ctypes.c_void_p(J.data_ptr())), self._h, "tbs_misfit")
         return q, J
+
+    def profile(self, enable: bool = True):
+        """Start (or stop) per-pass event timing on the plan's stream."""
+        self._sync_stream()
+        _check(library().tbs_profile_enable(self._h, int(enable)), self._h, "tbs_profile_enable")
+
+    def profile_read(self):
+        """{pass kind: (total ms, launches)} since profile(); resets."""
+        ms = (ctypes.c_double * 6)()
+        cnt = (ctypes.c_int64 * 6)()
+        _check(library().tbs_profile_read(self._h, ms, cnt), self._h, "tbs_profile_read")
+        return {k: (ms[i], int(cnt[i])) for i, k in enumerate(PASS_KINDS)}
 
     def speed_gradient(self, g, dVdc, out=None, accumulate: bool = False):
         torch = _torch()

@@ -51,6 +51,11 @@ struct tbs_plan {
   int64_t device_bytes = 0;
   bool green_ready = false;
   std::string err;
+  // per-pass event timing
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<std::pair<int, size_t>> ev_marks;  // (kind, index of the start event)
 };
 
 namespace {
@@ -162,6 +167,39 @@ int ensure_doubles(tbs_plan* p, double** buf, size_t* cap, size_t need) {
   return TBS_OK;
 }
 
+enum { PK_ROW_FIRST = 0, PK_ROW_MID = 1, PK_ROW_LAST = 2, PK_COL_CONV = 3, PK_COL_FWD = 4,
+       PK_COL_INV = 5, PK_N = 6 };
+
+hipEvent_t next_event(tbs_plan* p) {
+  if (p->ev_used == p->ev_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    p->ev_pool.push_back(e);
+  }
+  return p->ev_pool[p->ev_used++];
+}
+
+// Bracket a launch with events when profiling.
+struct ProfScope {
+  tbs_plan* p;
+  hipEvent_t e1 = nullptr;
+  ProfScope(tbs_plan* pl, int kind) : p(pl) {
+    if (!p->prof) return;
+    const size_t idx = p->ev_used;
+    hipEvent_t e0 = next_event(p);
+    e1 = next_event(p);
+    if (!e0 || !e1) {
+      e1 = nullptr;
+      return;
+    }
+    (void)hipEventRecord(e0, p->stream);
+    p->ev_marks.push_back({kind, idx});
+  }
+  ~ProfScope() {
+    if (e1) (void)hipEventRecord(e1, p->stream);
+  }
+};
+
 int row_blocks(const tbs_plan* p) {
   const int NR = tbs::row_rows_per_block((int)p->M[0], p->fp64);
   const int64_t rows = p->N[1] * p->N[2];
@@ -194,6 +232,7 @@ int run_row(tbs_plan* p, int in_mode, int acc, int out_spec, bool adjoint, const
   a.pstore = pstore_slot;
   a.cb = p->cb;
   a.xcd_remap = 1;
+  ProfScope ps(p, in_mode == tbs::ROW_IN_SOURCE ? PK_ROW_FIRST : (out_spec ? PK_ROW_MID : PK_ROW_LAST));
   TBS_LAUNCH(p, tbs::launch_row_pass(p->fp64, (int)p->M[0], a, row_blocks(p), p->stream));
   return TBS_OK;
 }
@@ -227,6 +266,7 @@ int run_cols(tbs_plan* p, bool adjoint) {
     a.g_sx = p->M[1] / 2 + 1;
     a.g_sm = 0;
     a.xcd_remap = 1;
+    ProfScope ps(p, PK_COL_CONV);
     TBS_LAUNCH(p, tbs::launch_col_pass(p->fp64, (int)p->M[1], (int)cb, a, p->stream));
     return TBS_OK;
   }
@@ -260,7 +300,10 @@ int run_cols(tbs_plan* p, bool adjoint) {
   f.out_rs = nkb * my * nz * cb;
   f.out_s1 = my * nz * cb;
   f.out_s0 = NZ * cb;
-  TBS_LAUNCH(p, tbs::launch_col_pass(p->fp64, (int)my, NC, f, p->stream));
+  {
+    ProfScope ps(p, PK_COL_FWD);
+    TBS_LAUNCH(p, tbs::launch_col_pass(p->fp64, (int)my, NC, f, p->stream));
+  }
 
   tbs::ColArgs z{};
   z.in = p->Yb;
@@ -286,7 +329,10 @@ int run_cols(tbs_plan* p, bool adjoint) {
   z.g_sx = (p->M[1] / 2 + 1) * (p->M[2] / 2 + 1);
   z.g_sm = p->M[2] / 2 + 1;
   z.xcd_remap = 1;
-  TBS_LAUNCH(p, tbs::launch_col_pass(p->fp64, (int)p->M[2], (int)cb, z, p->stream));
+  {
+    ProfScope ps(p, PK_COL_CONV);
+    TBS_LAUNCH(p, tbs::launch_col_pass(p->fp64, (int)p->M[2], (int)cb, z, p->stream));
+  }
 
   tbs::ColArgs iv = y;
   iv.in = p->Yb;
@@ -302,7 +348,10 @@ int run_cols(tbs_plan* p, bool adjoint) {
   iv.out_rs = nkb * ny * nz * cb;
   iv.out_s1 = ny * nz * cb;
   iv.out_s0 = NZ * cb;
-  TBS_LAUNCH(p, tbs::launch_col_pass(p->fp64, (int)my, NC, iv, p->stream));
+  {
+    ProfScope ps(p, PK_COL_INV);
+    TBS_LAUNCH(p, tbs::launch_col_pass(p->fp64, (int)my, NC, iv, p->stream));
+  }
   return TBS_OK;
 }
 
@@ -462,6 +511,7 @@ void tbs_plan_destroy(tbs_plan* p) {
   dev_free(p, p->ckpt, 0);
   q = p->jpart;
   dev_free(p, q, 0);
+  for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
   delete p;
 }
 
@@ -763,6 +813,33 @@ int tbs_speed_gradient(tbs_plan* p, const void* g, const void* dVdc, double* gra
   if (!p || !g || !dVdc || !grad_c) return fail(p, TBS_ERR_INVALID, "NULL argument");
   TBS_LAUNCH(p, tbs::launch_grad_assemble(g, p->batch, dVdc, grad_c, p->fp64, p->P, accumulate,
                                           p->stream));
+  return TBS_OK;
+}
+
+int tbs_profile_enable(tbs_plan* p, int enable) {
+  if (!p) return TBS_ERR_INVALID;
+  TBS_HIP(p, hipStreamSynchronize(p->stream));
+  p->prof = enable != 0;
+  p->ev_used = 0;
+  p->ev_marks.clear();
+  return TBS_OK;
+}
+
+int tbs_profile_read(tbs_plan* p, double* ms, int64_t* cnt) {
+  if (!p || !ms || !cnt) return fail(p, TBS_ERR_INVALID, "NULL argument");
+  TBS_HIP(p, hipStreamSynchronize(p->stream));
+  for (int k = 0; k < PK_N; ++k) {
+    ms[k] = 0.0;
+    cnt[k] = 0;
+  }
+  for (const auto& m : p->ev_marks) {
+    float t = 0.0f;
+    TBS_HIP(p, hipEventElapsedTime(&t, p->ev_pool[m.second], p->ev_pool[m.second + 1]));
+    ms[m.first] += t;
+    cnt[m.first] += 1;
+  }
+  p->ev_used = 0;
+  p->ev_marks.clear();
   return TBS_OK;
 }
 
