@@ -172,10 +172,12 @@ int tbs_harmonic_source(tbs_plan *plan, const void *p1_dev, const double *c_dev,
 int tbs_adjoint(tbs_plan *plan, const void *source, const void *potential, int nterms,
                 const void *adj_source, void *grad_out, double *residual_out, int flags);
 
-/* Receiver misfit.  rec_dev: dev int64 [nrec] flat spatial indices (distinct);
- * p_obs_dev: dev [B][nrec] plan dtype.  Writes q_dev (dev [B][P], zero except
- * q[b][rec[r]] = p[b][rec[r]] - p_obs[b][r]) and J_dev (dev double [1],
- * J = 1/2 sum |p[b][rec[r]] - p_obs[b][r]|^2). */
+/* Receiver misfit.  rec_dev: dev int64 [nrec] flat spatial indices (indices
+ * outside [0, P) are ignored); p_obs_dev: dev [B][nrec] plan dtype.  Writes
+ * q_dev (dev [B][P]: q = R^H r, i.e. zero except q[b][rec[r]] summing
+ * p[b][rec[r]] - p_obs[b][r] over receivers r on that cell; the summation
+ * order of three or more receivers sharing a cell is not fixed) and J_dev
+ * (dev double [1], J = 1/2 sum |p[b][rec[r]] - p_obs[b][r]|^2). */
 int tbs_misfit(tbs_plan *plan, const void *p_dev, const int64_t *rec_dev, int nrec,
                const void *p_obs_dev, void *q_dev, double *J_dev);
 

@@ -18,7 +18,8 @@ from typing import Optional, Sequence, Tuple
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libtbs.so")
+# TBS_LIBRARY overrides the library file (e.g. an alternative tuning build).
+LIB_PATH = os.environ.get("TBS_LIBRARY", os.path.join(HERE, "libtbs.so"))
 
 TBS_C64, TBS_C128 = 0, 1
 TBS_OK = 0

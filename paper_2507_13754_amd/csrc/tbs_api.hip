@@ -114,8 +114,8 @@ bool is_fin(double v) { return std::isfinite(v); }
 
 // Twiddle table of one FFT length in the stage layout of tbs_fft.hpp, built in
 // extended precision and rounded once.
-std::vector<zd> twiddles(int M) {
-  const int E = tbs::fft_elems_per_thread(M);
+std::vector<zd> twiddles(int M, bool fp64) {
+  const int E = tbs::fft_elems_per_thread(M, fp64);
   const tbs::Stages st = tbs::make_stages(M, E);
   std::vector<zd> out;
   out.reserve(M);
@@ -136,7 +136,7 @@ std::vector<zd> twiddles(int M) {
 }
 
 int upload_twiddles(tbs_plan* p, int M, bool fp64, void** dst) {
-  std::vector<zd> t = twiddles(M);
+  std::vector<zd> t = twiddles(M, fp64);
   size_t bytes = t.size() * (fp64 ? 16 : 8);
   if (bytes == 0) bytes = 16;
   int rc = dev_alloc(p, dst, bytes);

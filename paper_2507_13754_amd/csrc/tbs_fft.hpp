@@ -271,8 +271,11 @@ __device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
 __host__ __device__ constexpr int lds_len(int M) { return M + M / 16 + 4; }
 
 // One Stockham stage S and the exchange to stage S+1 (recursively).
-template <typename T, int M, int E, bool INV, int S>
-__device__ __forceinline__ void fft_stages(cx<T> (&v)[E], cx<T>* __restrict__ sh,
+// SPLIT: exchange real and imaginary parts in two rounds through a scalar LDS
+// buffer of M (+pad) values, halving the LDS a line needs (four barriers per
+// exchange instead of two).  Otherwise complex values go through LDS at once.
+template <typename T, int M, int E, bool INV, bool SPLIT, int S>
+__device__ __forceinline__ void fft_stages(cx<T> (&v)[E], void* __restrict__ shv,
                                            const cx<T>* __restrict__ tw, int t) {
   constexpr Stages st = make_stages(M, E);
   static_assert(st.n > 0, "length not 5-smooth");
@@ -297,30 +300,59 @@ __device__ __forceinline__ void fft_stages(cx<T> (&v)[E], cx<T>* __restrict__ sh
       }
     }
     dft<R, INV>(a);
-    if constexpr (LAST) {
+    if constexpr (LAST || SPLIT) {
 #pragma unroll
       for (int r = 0; r < R; ++r) v[q + r * NB] = a[r];
     } else {
+      cx<T>* sh = (cx<T>*)shv;
       const int base = (b / L) * L * R + k;
 #pragma unroll
       for (int r = 0; r < R; ++r) sh[lpad(base + r * L)] = a[r];
     }
   }
   if constexpr (!LAST) {
-    __syncthreads();
+    if constexpr (SPLIT) {
+      T* sh = (T*)shv;
 #pragma unroll
-    for (int j = 0; j < E; ++j) v[j] = sh[lpad(t + j * TPT)];
-    __syncthreads();
-    fft_stages<T, M, E, INV, S + 1>(v, sh, tw, t);
+      for (int q = 0; q < NB; ++q) {
+        const int b = t + q * TPT;
+        const int base = (b / L) * L * R + (b % L);
+#pragma unroll
+        for (int r = 0; r < R; ++r) sh[lpad(base + r * L)] = v[q + r * NB].x;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < E; ++j) v[j].x = sh[lpad(t + j * TPT)];
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        const int b = t + q * TPT;
+        const int base = (b / L) * L * R + (b % L);
+#pragma unroll
+        for (int r = 0; r < R; ++r) sh[lpad(base + r * L)] = v[q + r * NB].y;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < E; ++j) v[j].y = sh[lpad(t + j * TPT)];
+      __syncthreads();
+    } else {
+      cx<T>* sh = (cx<T>*)shv;
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < E; ++j) v[j] = sh[lpad(t + j * TPT)];
+      __syncthreads();
+    }
+    fft_stages<T, M, E, INV, SPLIT, S + 1>(v, shv, tw, t);
   }
 }
 
 // Full transform of the thread's E registers (strided layout in and out).
 // Every thread of the block must call it (it contains block barriers).
-template <typename T, int M, int E, bool INV>
-__device__ __forceinline__ void fft(cx<T> (&v)[E], cx<T>* __restrict__ sh,
+// shv: this line's LDS buffer, lds_len(M) elements of T (SPLIT) or cx<T>.
+template <typename T, int M, int E, bool INV, bool SPLIT>
+__device__ __forceinline__ void fft(cx<T> (&v)[E], void* __restrict__ shv,
                                     const cx<T>* __restrict__ tw, int t) {
-  fft_stages<T, M, E, INV, 0>(v, sh, tw, t);
+  fft_stages<T, M, E, INV, SPLIT, 0>(v, shv, tw, t);
 }
 
 }  // namespace tbs

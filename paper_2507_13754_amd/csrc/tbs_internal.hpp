@@ -56,7 +56,7 @@ enum ColOp { COL_CONV = 0, COL_FWD = 1, COL_INV = 2, COL_FULL = 3 };
 
 // Lengths the library has kernels for.
 bool fft_length_supported(int M);
-int fft_elems_per_thread(int M);
+int fft_elems_per_thread(int M, bool fp64);
 int row_rows_per_block(int M, bool fp64);
 int spectral_block(int My, bool fp64);
 int col_max_cols(int M, bool fp64);  // widest column block that fits LDS

@@ -184,8 +184,8 @@ int launch_harmonic_source(const void* p1, const double* c, void* S2, bool fp64,
   return (int)hipGetLastError();
 }
 
-// Receiver misfit: r = p[b][rec] - p_obs[b][r]; q[b][rec] = r (q zeroed by the
-// caller, receivers distinct); jpart[b][r] = |r|^2.
+// Receiver misfit: r = p[b][rec] - p_obs[b][r]; q[b][rec] += r (q zeroed by
+// the caller; R^H sums receivers that share a cell); jpart[b][r] = |r|^2.
 template <typename T>
 __global__ void __launch_bounds__(256) k_misfit(const cx<T>* p, const int64_t* rec,
                                                 const cx<T>* pobs, cx<T>* q, double* jpart,
@@ -201,7 +201,8 @@ __global__ void __launch_bounds__(256) k_misfit(const cx<T>* p, const int64_t* r
   }
   const int64_t idx = (int64_t)b * P + ri;
   const cx<T> d = p[idx] - pobs[i];
-  q[idx] = d;
+  atomicAdd(&q[idx].x, d.x);
+  atomicAdd(&q[idx].y, d.y);
   jpart[i] = (double)d.x * d.x + (double)d.y * d.y;
 }
 

@@ -15,8 +15,24 @@
 // LDS is used only for the exchanges between radix stages.  Lines are read
 // and written in contiguous kBlock-wide column blocks so that every HBM access
 // is a full, coalesced segment.
+#include <type_traits>
+
 #include "tbs_fft.hpp"
 #include "tbs_internal.hpp"
+
+// Tuning knobs (compile-time; the defaults are the measured best on MI355X).
+#ifndef TBS_E_LONG_F32
+#define TBS_E_LONG_F32 16   // values per thread, FP32 lines of 2048+
+#endif
+#ifndef TBS_SPLIT_MIN
+#define TBS_SPLIT_MIN 1024  // shortest line that exchanges re/im separately
+#endif
+#ifndef TBS_NR_F32
+#define TBS_NR_F32 4        // rows per FP32 row-pass block
+#endif
+#ifndef TBS_MIN_WAVES
+#define TBS_MIN_WAVES 0     // occupancy hint for the long-line passes (0: none)
+#endif
 
 namespace tbs {
 
@@ -52,8 +68,8 @@ __device__ __forceinline__ int fold(int k, int m) { return k <= (m >> 1) ? k : m
 
 // ---------------------------------------------------------------- row pass --
 
-template <typename T, int M, int E, int NR, int CB>
-__global__ void __launch_bounds__(NR * (M / E)) k_row_pass(RowArgs a) {
+template <typename T, int M, int E, int NR, int CB, bool SPLIT>
+__global__ void __launch_bounds__(NR * (M / E), (M >= 2048 ? TBS_MIN_WAVES : 0)) k_row_pass(RowArgs a) {
   constexpr int TPT = M / E;
   constexpr int NKB = M / CB;
   constexpr int LD = lds_len(M);
@@ -61,7 +77,8 @@ __global__ void __launch_bounds__(NR * (M / E)) k_row_pass(RowArgs a) {
   constexpr int NW = (NT + 63) / 64;
   static_assert(TPT % CB == 0, "line too short for the column block");
   static_assert(E % 2 == 0, "E must be even");
-  __shared__ cx<T> sh[NR * LD];
+  using LdsT = typename std::conditional<SPLIT, T, cx<T>>::type;
+  __shared__ LdsT sh[NR * LD];
   __shared__ double red[2 * NW];
 
   const int tid = threadIdx.x;
@@ -75,7 +92,7 @@ __global__ void __launch_bounds__(NR * (M / E)) k_row_pass(RowArgs a) {
   const int nblk = (a.nrows + NR - 1) / NR;
   const int row = rb * NR + r;
   const bool valid = row < a.nrows;
-  cx<T>* shr = sh + r * LD;
+  LdsT* shr = sh + r * LD;
   const cx<T>* tw = (const cx<T>*)a.tw;
   cx<T>* X = (cx<T>*)a.X;
   const int64_t P = (int64_t)a.nrows * a.nx;
@@ -94,7 +111,7 @@ __global__ void __launch_bounds__(NR * (M / E)) k_row_pass(RowArgs a) {
       const int kx = t + j * TPT;
       v[j] = valid ? X[xbase + (int64_t)(kx / CB) * kbstride + (kx % CB)] : cx<T>{T(0), T(0)};
     }
-    fft<T, M, E, true>(v, shr, tw, t);
+    fft<T, M, E, true, SPLIT>(v, shr, tw, t);
     cx<T>* p = (cx<T>*)a.p;
     const cx<T>* Vp = (const cx<T>*)a.V;
 #pragma unroll
@@ -170,7 +187,7 @@ __global__ void __launch_bounds__(NR * (M / E)) k_row_pass(RowArgs a) {
   }
 
   if (a.out_spec) {
-    fft<T, M, E, false>(v, shr, tw, t);
+    fft<T, M, E, false, SPLIT>(v, shr, tw, t);
     if (valid) {
 #pragma unroll
       for (int j = 0; j < E; ++j) {
@@ -183,13 +200,14 @@ __global__ void __launch_bounds__(NR * (M / E)) k_row_pass(RowArgs a) {
 
 // ------------------------------------------------------------- column pass --
 
-template <typename T, int M, int E, int NC, int OP>
-__global__ void __launch_bounds__(NC * (M / E)) k_col_pass(ColArgs a) {
+template <typename T, int M, int E, int NC, int OP, bool SPLIT>
+__global__ void __launch_bounds__(NC * (M / E), (M >= 2048 ? TBS_MIN_WAVES : 0)) k_col_pass(ColArgs a) {
   constexpr int TPT = M / E;
   constexpr int LD = lds_len(M);
   constexpr bool HALF_IN = (OP == COL_CONV || OP == COL_FWD);
   constexpr bool HALF_OUT = (OP == COL_CONV || OP == COL_INV);
-  __shared__ cx<T> sh[NC * LD];
+  using LdsT = typename std::conditional<SPLIT, T, cx<T>>::type;
+  __shared__ LdsT sh[NC * LD];
 
   const int tid = threadIdx.x;
   const int col = tid % NC;
@@ -200,7 +218,7 @@ __global__ void __launch_bounds__(NC * (M / E)) k_col_pass(ColArgs a) {
   const int i0 = rest % a.n0;
   const int i1 = rest / a.n0;
   const bool cvalid = (i0 * a.zcols + col / a.cb) < a.zlim;
-  cx<T>* shc = sh + col * LD;
+  LdsT* shc = sh + col * LD;
   const cx<T>* tw = (const cx<T>*)a.tw;
   const cx<T>* in = (const cx<T>*)a.in;
   cx<T>* out = (cx<T>*)a.out;
@@ -214,7 +232,7 @@ __global__ void __launch_bounds__(NC * (M / E)) k_col_pass(ColArgs a) {
     const bool ld = (!HALF_IN || j < E / 2) && cvalid && pos < a.n_in;
     v[j] = ld ? in[ib + pos * a.in_astride] : cx<T>{T(0), T(0)};
   }
-  if constexpr (OP != COL_INV) fft<T, M, E, false>(v, shc, tw, tt);
+  if constexpr (OP != COL_INV) fft<T, M, E, false, SPLIT>(v, shc, tw, tt);
   if constexpr (OP == COL_CONV) {
     const cx<T>* g = (const cx<T>*)a.ghat;
     const int kx = i1 * a.cb + (col % a.cb);
@@ -225,7 +243,7 @@ __global__ void __launch_bounds__(NC * (M / E)) k_col_pass(ColArgs a) {
       v[j] = a.conj_g ? cmulc(v[j], gv) : cmul(v[j], gv);
     }
   }
-  if constexpr (OP == COL_CONV || OP == COL_INV) fft<T, M, E, true>(v, shc, tw, tt);
+  if constexpr (OP == COL_CONV || OP == COL_INV) fft<T, M, E, true, SPLIT>(v, shc, tw, tt);
   if (cvalid) {
 #pragma unroll
     for (int j = 0; j < E; ++j) {
@@ -236,12 +254,13 @@ __global__ void __launch_bounds__(NC * (M / E)) k_col_pass(ColArgs a) {
 }
 
 // Plain in-place FFT of contiguous rows [nrows][M] (tabulation, FP64).
-template <typename T, int M, int E, int NR>
+template <typename T, int M, int E, int NR, bool SPLIT>
 __global__ void __launch_bounds__(NR * (M / E)) k_row_fft_full(cx<T>* data, const cx<T>* tw,
                                                                int nrows, int inverse) {
   constexpr int TPT = M / E;
   constexpr int LD = lds_len(M);
-  __shared__ cx<T> sh[NR * LD];
+  using LdsT = typename std::conditional<SPLIT, T, cx<T>>::type;
+  __shared__ LdsT sh[NR * LD];
   const int tid = threadIdx.x;
   const int r = tid / TPT;
   const int t = tid % TPT;
@@ -252,9 +271,9 @@ __global__ void __launch_bounds__(NR * (M / E)) k_row_fft_full(cx<T>* data, cons
 #pragma unroll
   for (int j = 0; j < E; ++j) v[j] = valid ? d[t + j * TPT] : cx<T>{T(0), T(0)};
   if (inverse)
-    fft<T, M, E, true>(v, sh + r * LD, tw, t);
+    fft<T, M, E, true, SPLIT>(v, sh + r * LD, tw, t);
   else
-    fft<T, M, E, false>(v, sh + r * LD, tw, t);
+    fft<T, M, E, false, SPLIT>(v, sh + r * LD, tw, t);
   if (valid) {
 #pragma unroll
     for (int j = 0; j < E; ++j) d[t + j * TPT] = v[j];
@@ -277,28 +296,36 @@ bool fft_length_supported(int M) {
   }
 }
 
-constexpr int elems_per_thread(int M) { return M <= 64 ? 4 : (M <= 512 ? 8 : 16); }
-int fft_elems_per_thread(int M) { return elems_per_thread(M); }
+// Values per thread: more for long FP32 lines (more independent work per
+// thread, fewer threads), 16 for long FP64 lines (register budget).
+constexpr int elems_per_thread(int M, bool fp64) {
+  return M <= 64 ? 4 : (M <= 512 ? 8 : ((M <= 1024 || fp64) ? 16 : TBS_E_LONG_F32));
+}
+int fft_elems_per_thread(int M, bool fp64) { return elems_per_thread(M, fp64); }
+// Long lines exchange real and imaginary parts separately (half the LDS).
+constexpr bool split_lds(int M) { return M >= TBS_SPLIT_MIN; }
 
-// Rows per row-pass block: LDS (160 KB per CU) holds NR lines of M values.
+// Rows per row-pass block: LDS (160 KB per CU) holds NR lines.
 constexpr int rows_per_block(int M, bool fp64) {
-  return fp64 ? (M >= 4096 ? 2 : 4) : 4;
+  return fp64 ? ((M >= 4096 || (M >= 2048 && !split_lds(M))) ? 2 : 4) : (M >= 2048 ? TBS_NR_F32 : 4);
 }
 int row_rows_per_block(int M, bool fp64) { return rows_per_block(M, fp64); }
 
 // Contiguous spectral columns per block of the intermediate layout: 4, except
-// FP64 with columns of 4096+ values, where 4 lines would not fit in LDS.
+// FP64 with columns of 4096+ values (two such lines per block fit LDS twice).
 int spectral_block(int My, bool fp64) { return (fp64 && My >= 4096) ? 2 : 4; }
 
 template <typename T, int M>
 static int row_launch(const RowArgs& a, int nblk_rows, hipStream_t s) {
-  constexpr int E = elems_per_thread(M);
-  constexpr int NR = rows_per_block(M, sizeof(T) == 8);
+  constexpr bool F64 = sizeof(T) == 8;
+  constexpr int E = elems_per_thread(M, F64);
+  constexpr int NR = rows_per_block(M, F64);
+  constexpr bool SP = split_lds(M);
   const int grid = nblk_rows * a.nrhs;
   if (a.cb == 4) {
-    hipLaunchKernelGGL((k_row_pass<T, M, E, NR, 4>), dim3(grid), dim3(NR * (M / E)), 0, s, a);
+    hipLaunchKernelGGL((k_row_pass<T, M, E, NR, 4, SP>), dim3(grid), dim3(NR * (M / E)), 0, s, a);
   } else if (a.cb == 2) {
-    hipLaunchKernelGGL((k_row_pass<T, M, E, NR, 2>), dim3(grid), dim3(NR * (M / E)), 0, s, a);
+    hipLaunchKernelGGL((k_row_pass<T, M, E, NR, 2, SP>), dim3(grid), dim3(NR * (M / E)), 0, s, a);
   } else {
     return (int)hipErrorInvalidValue;
   }
@@ -319,22 +346,23 @@ int launch_row_pass(bool fp64, int M, const RowArgs& a, int nblk_rows, hipStream
 
 template <typename T, int M, int NC>
 static int col_launch(const ColArgs& a, hipStream_t s) {
-  constexpr int E = elems_per_thread(M);
+  constexpr int E = elems_per_thread(M, sizeof(T) == 8);
+  constexpr bool SP = split_lds(M);
   const int grid = a.nrhs * a.n1 * a.n0;
   const dim3 blk(NC * (M / E));
   switch (a.op) {
     case COL_CONV:
-      hipLaunchKernelGGL((k_col_pass<T, M, E, NC, COL_CONV>), dim3(grid), blk, 0, s, a);
+      hipLaunchKernelGGL((k_col_pass<T, M, E, NC, COL_CONV, SP>), dim3(grid), blk, 0, s, a);
       break;
     case COL_FWD:
-      hipLaunchKernelGGL((k_col_pass<T, M, E, NC, COL_FWD>), dim3(grid), blk, 0, s, a);
+      hipLaunchKernelGGL((k_col_pass<T, M, E, NC, COL_FWD, SP>), dim3(grid), blk, 0, s, a);
       break;
     case COL_INV:
-      hipLaunchKernelGGL((k_col_pass<T, M, E, NC, COL_INV>), dim3(grid), blk, 0, s, a);
+      hipLaunchKernelGGL((k_col_pass<T, M, E, NC, COL_INV, SP>), dim3(grid), blk, 0, s, a);
       break;
     default:
       if constexpr (sizeof(T) == 8) {
-        hipLaunchKernelGGL((k_col_pass<T, M, E, NC, COL_FULL>), dim3(grid), blk, 0, s, a);
+        hipLaunchKernelGGL((k_col_pass<T, M, E, NC, COL_FULL, SP>), dim3(grid), blk, 0, s, a);
       } else {
         return (int)hipErrorInvalidValue;
       }
@@ -343,7 +371,7 @@ static int col_launch(const ColArgs& a, hipStream_t s) {
 }
 
 constexpr bool col_fits(int M, int NC, int esz) {
-  return (long)NC * lds_len(M) * esz <= 160L * 1024;
+  return (long)NC * lds_len(M) * (split_lds(M) ? esz / 2 : esz) <= 160L * 1024;
 }
 int col_max_cols(int M, bool fp64) {
   const int esz = fp64 ? 16 : 8;
@@ -379,9 +407,9 @@ int launch_col_pass(bool fp64, int M, int NC, const ColArgs& a, hipStream_t s) {
 
 template <int M>
 static int rowfull_launch(void* data, const void* tw, int nrows, int inverse, hipStream_t s) {
-  constexpr int E = elems_per_thread(M);
+  constexpr int E = elems_per_thread(M, true);
   constexpr int NR = rows_per_block(M, true);
-  hipLaunchKernelGGL((k_row_fft_full<double, M, E, NR>), dim3((nrows + NR - 1) / NR),
+  hipLaunchKernelGGL((k_row_fft_full<double, M, E, NR, split_lds(M)>), dim3((nrows + NR - 1) / NR),
                      dim3(NR * (M / E)), 0, s, (cx<double>*)data, (const cx<double>*)tw, nrows,
                      inverse);
   return (int)hipGetLastError();

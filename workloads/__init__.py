@@ -261,7 +261,8 @@ def adjoint2d(n: int = 1024, nfreq: int = 16, nsrc: int = 8, nrec: int = 128,
     """1024^2 grid at dx = lambda/6 at 6 MHz; model map blobs +-3 % (seed 5);
     true map = model * (1 + 0.02 h), h a clipped blob field (seed 50); 8 point
     sources on row 8, columns 64 + 128 s; 128 receivers on row N-9, columns
-    4 + 8 r; 64 FD pixels (seed 55).  Grid positions scale with ``n``."""
+    4 + 8 r; 64 FD pixels (seed 55).  Grid positions scale with ``n``
+    (receivers that would share a cell after scaling are merged)."""
     dx = C0 / 6.0e6 / 6.0
     extent = n * dx
     scale = n / 1024.0
@@ -273,8 +274,8 @@ def adjoint2d(n: int = 1024, nfreq: int = 16, nsrc: int = 8, nrec: int = 128,
     s = np.zeros((nsrc, n, n), dtype=np.complex128)
     for i, cell in enumerate(src_cells):
         s[(i,) + cell] = 1.0 / dx ** 2
-    rec = np.array([(n - 9, min(int(round((4 + 8 * r) * scale)), n - 1)) for r in range(nrec)],
-                   dtype=np.int64)
+    cols = sorted({min(int(round((4 + 8 * r) * scale)), n - 1) for r in range(nrec)})
+    rec = np.array([(n - 9, col) for col in cols], dtype=np.int64)   # distinct cells
     rng = np.random.Generator(np.random.PCG64(seed * 11))
     lo, hi = int(0.2 * n), int(0.8 * n)
     fd = np.stack([rng.integers(lo, hi, 64), rng.integers(lo, hi, 64)], axis=1).astype(np.int64)
