@@ -255,8 +255,10 @@ int run_cols(tbs_plan* p, bool adjoint) {
     a.in_rs = a.out_rs = nkb * p->N[1] * cb;
     a.in_s1 = a.out_s1 = p->N[1] * cb;
     a.in_s0 = a.out_s0 = 0;
+    const int nc = tbs::conv_cols_per_block((int)p->M[1], p->fp64, (int)cb);
     a.nrhs = p->batch;
-    a.n1 = (int)nkb;
+    a.sub = (int)cb / nc;
+    a.n1 = (int)nkb * a.sub;
     a.n0 = 1;
     a.cb = (int)cb;
     a.zcols = 0;
@@ -267,7 +269,7 @@ int run_cols(tbs_plan* p, bool adjoint) {
     a.g_sm = 0;
     a.xcd_remap = 1;
     ProfScope ps(p, PK_COL_CONV);
-    TBS_LAUNCH(p, tbs::launch_col_pass(p->fp64, (int)p->M[1], (int)cb, a, p->stream));
+    TBS_LAUNCH(p, tbs::launch_col_pass(p->fp64, (int)p->M[1], nc, a, p->stream));
     return TBS_OK;
   }
   // 3D: y forward (A -> B), z convolution (in B), y inverse (B -> A).
@@ -276,6 +278,7 @@ int run_cols(tbs_plan* p, bool adjoint) {
   const int NC = NZ * (int)cb;
   const int nzb = (int)((nz + NZ - 1) / NZ);
   tbs::ColArgs y{};
+  y.sub = 1;
   y.tw = p->tw[1];
   y.nrhs = p->batch;
   y.n1 = (int)nkb;
@@ -306,6 +309,7 @@ int run_cols(tbs_plan* p, bool adjoint) {
   }
 
   tbs::ColArgs z{};
+  z.sub = 1;
   z.in = p->Yb;
   z.out = p->Yb;
   z.tw = p->tw[2];
@@ -618,6 +622,7 @@ int tbs_green_tabulate(tbs_plan* p) {
   for (int ax = 1; ax < p->ndim && !e; ++ax) {
     const int nc = tbs::col_max_cols((int)M3[ax], true);
     tbs::ColArgs a{};
+    a.sub = 1;
     a.in = W;
     a.out = W;
     a.tw = tw64[ax];

@@ -47,6 +47,7 @@ struct ColArgs {
   int64_t in_rs, in_s1, in_s0, out_rs, out_s1, out_s0;
   int nrhs, n1, n0;
   int cb;               // spectral block width of the layout
+  int sub;              // blocks per layout block (block holds cb/sub columns); 1 otherwise
   int zcols, zlim;      // column validity: i0*zcols + col/cb < zlim
   int mx, mm;           // fold sizes of kx (= i1*cb + col%cb) and kmid (= i0)
   int64_t g_sx, g_sm;   // table strides for fold(kx), fold(kmid)
@@ -60,6 +61,7 @@ int fft_elems_per_thread(int M, bool fp64);
 int row_rows_per_block(int M, bool fp64);
 int spectral_block(int My, bool fp64);
 int col_max_cols(int M, bool fp64);  // widest column block that fits LDS
+int conv_cols_per_block(int M, bool fp64, int cb);  // columns per convolution block
 // Launchers (return hipError_t as int).
 int launch_row_pass(bool fp64, int M, const RowArgs& a, int nblk_rows, hipStream_t s);
 int launch_col_pass(bool fp64, int M, int NC, const ColArgs& a, hipStream_t s);

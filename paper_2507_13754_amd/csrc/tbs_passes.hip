@@ -25,10 +25,19 @@
 #define TBS_E_LONG_F32 16   // values per thread, FP32 lines of 2048+
 #endif
 #ifndef TBS_SPLIT_MIN
-#define TBS_SPLIT_MIN 1024  // shortest line that exchanges re/im separately
+#define TBS_SPLIT_MIN 1000000  // shortest line that exchanges re/im separately
 #endif
 #ifndef TBS_NR_F32
-#define TBS_NR_F32 4        // rows per FP32 row-pass block
+#define TBS_NR_F32 2        // rows per FP32 row-pass block (lines of 2048+)
+#endif
+#ifndef TBS_NC_F32
+#define TBS_NC_F32 2        // columns per FP32 column-convolution block (<= layout block)
+#endif
+#ifndef TBS_NR_F64
+#define TBS_NR_F64 2        // rows per FP64 row-pass block (lines of 4096)
+#endif
+#ifndef TBS_NC_F64
+#define TBS_NC_F64 2        // columns per FP64 column-convolution block (lines of 2048+)
 #endif
 #ifndef TBS_MIN_WAVES
 #define TBS_MIN_WAVES 0     // occupancy hint for the long-line passes (0: none)
@@ -222,8 +231,11 @@ __global__ void __launch_bounds__(NC * (M / E), (M >= 2048 ? TBS_MIN_WAVES : 0))
   const cx<T>* tw = (const cx<T>*)a.tw;
   const cx<T>* in = (const cx<T>*)a.in;
   cx<T>* out = (cx<T>*)a.out;
-  const int64_t ib = rhs * a.in_rs + i1 * a.in_s1 + i0 * a.in_s0 + col;
-  const int64_t ob = rhs * a.out_rs + i1 * a.out_s1 + i0 * a.out_s0 + col;
+  // a.sub > 1: the block holds NC of the cb columns of layout block i1 / sub
+  const int blk = i1 / a.sub;
+  const int c0 = (i1 % a.sub) * NC;
+  const int64_t ib = rhs * a.in_rs + blk * a.in_s1 + i0 * a.in_s0 + c0 + col;
+  const int64_t ob = rhs * a.out_rs + blk * a.out_s1 + i0 * a.out_s0 + c0 + col;
 
   cx<T> v[E];
 #pragma unroll
@@ -235,7 +247,7 @@ __global__ void __launch_bounds__(NC * (M / E), (M >= 2048 ? TBS_MIN_WAVES : 0))
   if constexpr (OP != COL_INV) fft<T, M, E, false, SPLIT>(v, shc, tw, tt);
   if constexpr (OP == COL_CONV) {
     const cx<T>* g = (const cx<T>*)a.ghat;
-    const int kx = i1 * a.cb + (col % a.cb);
+    const int kx = blk * a.cb + c0 + (col % a.cb);
     const int64_t gb = fold(kx, a.mx) * a.g_sx + fold(i0, a.mm) * a.g_sm;
 #pragma unroll
     for (int j = 0; j < E; ++j) {
@@ -307,7 +319,8 @@ constexpr bool split_lds(int M) { return M >= TBS_SPLIT_MIN; }
 
 // Rows per row-pass block: LDS (160 KB per CU) holds NR lines.
 constexpr int rows_per_block(int M, bool fp64) {
-  return fp64 ? ((M >= 4096 || (M >= 2048 && !split_lds(M))) ? 2 : 4) : (M >= 2048 ? TBS_NR_F32 : 4);
+  return fp64 ? (M >= 4096 ? TBS_NR_F64 : (M >= 2048 && !split_lds(M) ? 2 : 4))
+              : (M >= 2048 ? TBS_NR_F32 : 4);
 }
 int row_rows_per_block(int M, bool fp64) { return rows_per_block(M, fp64); }
 
@@ -373,6 +386,11 @@ static int col_launch(const ColArgs& a, hipStream_t s) {
 constexpr bool col_fits(int M, int NC, int esz) {
   return (long)NC * lds_len(M) * (split_lds(M) ? esz / 2 : esz) <= 160L * 1024;
 }
+int conv_cols_per_block(int M, bool fp64, int cb) {
+  const int want = M >= 2048 ? (fp64 ? TBS_NC_F64 : TBS_NC_F32) : cb;
+  return want < cb ? want : cb;
+}
+
 int col_max_cols(int M, bool fp64) {
   const int esz = fp64 ? 16 : 8;
   return col_fits(M, 4, esz) ? 4 : (col_fits(M, 2, esz) ? 2 : 1);
@@ -386,6 +404,9 @@ static int col_launch_nc(int NC, const ColArgs& a, hipStream_t s) {
   }
   if constexpr (col_fits(M, 2, esz)) {
     if (NC == 2) return col_launch<T, M, 2>(a, s);
+  }
+  if constexpr (M >= 2048) {
+    if (NC == 1) return col_launch<T, M, 1>(a, s);
   }
   if constexpr (M <= 512 && col_fits(M, 16, esz)) {
     if (NC == 16) return col_launch<T, M, 16>(a, s);
