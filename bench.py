@@ -34,7 +34,7 @@ def log(*a):
 
 def kernel_sources_hash() -> str:
     h = hashlib.sha256()
-    for f in ("tbs_passes.hip", "tbs_fft.hpp", "tbs_internal.hpp"):
+    for f in ("tbs_passes.hpp", "tbs_fft.hpp", "tbs_internal.hpp"):
         with open(os.path.join(ROOT, "paper_2507_13754_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -149,6 +149,185 @@ def read_counters(workload: str, kernel: str):
     return d.get("traffic_bytes_per_launch")
 
 
+def grid_step_bytes(grid, padded, B, esz, kahan, L):
+    N = (grid[-1], grid[-2], grid[-3] if len(grid) == 3 else 1)
+    M = (padded[0], padded[1], padded[2] if len(grid) == 3 else 1)
+    g = (M[0] // 2 + 1) * (M[1] // 2 + 1) * ((M[2] // 2 + 1) if len(grid) == 3 else 1) * esz
+    return step_bytes(len(grid), N, M, B, esz, kahan, g, L)
+
+
+def run_broadband(dev, steps: int, warmup: int, fp64: bool, cpu_seconds: float):
+    """48 frequencies (2-8 MHz) on their own lambda/6 grids over 4 x 4 cm, 16
+    steering angles each, 25 terms: one batch, replayed as one graph."""
+    import torch
+    import workloads
+    import paper_2507_13754_amd as tbs
+    out = {}
+    for name, dtype in (("c64", torch.complex64), ("c128", torch.complex128)):
+        if name == "c128" and not fp64:
+            continue
+        plans, srcs, pots, gpts, nbytes = [], [], [], 0, 0
+        t0 = time.perf_counter()
+        for i in range(len(workloads.BROADBAND_FREQS)):
+            c = workloads.broadband(i)
+            k0 = tbs.background_k0(c.omega, c.c0, c.alpha0, c.y)
+            p = tbs.Plan(c.grid, c.dx, k0, dtype=dtype, batch=c.sources.shape[0]).tabulate()
+            plans.append(p)
+            srcs.append(torch.from_numpy(c.sources).to(dev, dtype))
+            pots.append(p.potential(torch.from_numpy(c.c).to(dev), c.omega, c.c0, c.alpha0, c.y))
+            gpts += c.points * c.nterms * c.sources.shape[0]
+            nbytes += grid_step_bytes(c.grid, p.padded, c.sources.shape[0], 8 if name == "c64" else 16,
+                                      name == "c64", c.nterms)
+            L = c.nterms
+            del c
+        log(f"[bench] broadband {name}: 48 plans built in {time.perf_counter() - t0:.1f} s")
+        batch = tbs.Batch(plans)
+        outs = batch.solve(srcs, pots, L)
+        ms, wall = time_solves_fn(lambda: batch.solve(srcs, pots, L, outs=outs), steps, warmup)
+        log(f"[bench] broadband {name}: {ms:.2f} ms/step")
+        out[name] = dict(ms=ms, value=gpts / (ms * 1e-3), bytes=nbytes,
+                         GBps=nbytes / (ms * 1e-3) / 1e9, outs=[o.cpu() for o in outs],
+                         lengths=sorted({p.padded[0] for p in plans}))
+        batch.close()
+        for p in plans:
+            p.close()
+        del srcs, pots, outs
+        torch.cuda.empty_cache()
+    res = {"workload": "broadband: 48 frequencies 2-8 MHz, lambda/6 grids over 4x4 cm (312^2..1247^2), "
+                       "16 steering angles each, 25 terms, one recorded graph per solve",
+           "value": out["c64"]["value"], "unit": "grid-point·terms/s", "ms_per_step": out["c64"]["ms"],
+           "alg_bytes_per_step": out["c64"]["bytes"], "achieved_GBps": out["c64"]["GBps"],
+           "frac": out["c64"]["GBps"] / HBM_PEAK_GBS, "padded_lengths": out["c64"]["lengths"]}
+    if "c128" in out:
+        errs = []
+        for a, b in zip(out["c64"]["outs"], out["c128"]["outs"]):
+            a = a.numpy().astype(np.complex128)
+            b = b.numpy()
+            errs.append(max(float(np.linalg.norm(a[k] - b[k]) / np.linalg.norm(b[k])) for k in range(a.shape[0])))
+        res["fp64_plain"] = {"value": out["c128"]["value"], "ms_per_step": out["c128"]["ms"],
+                             "achieved_GBps": out["c128"]["GBps"], "frac": out["c128"]["GBps"] / HBM_PEAK_GBS}
+        res["speedup_fp32_vs_fp64"] = out["c128"]["ms"] / out["c64"]["ms"]
+        res["rel_l2_fp32_vs_fp64_max"] = max(errs)
+    if cpu_seconds > 0:
+        res["cpu_baseline"] = cpu_baseline(workloads.broadband(0), cpu_seconds)
+    return res
+
+
+def time_solves_fn(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps, (time.perf_counter() - t0) / steps * 1e3
+
+
+def run_harmonic3d(dev, steps: int, warmup: int, fp64: bool):
+    """256^3 at lambda/6 (3 MHz), 3D blob tissue; fundamental (24 terms), the
+    second-harmonic source, then the 6 MHz solve (24 terms).  One step = both
+    series and the source kernel."""
+    import torch
+    import workloads
+    import paper_2507_13754_amd as tbs
+    c = workloads.harmonic3d()
+    cd = torch.from_numpy(c.c).to(dev)
+    om = c.omega
+    res = {"workload": "harmonic3d: 256^3 grid, dx=lambda/6 at 3 MHz, 11 3D blobs c0 +-2%, rho=1000, B/A=7, "
+                       "fundamental 24 terms + second harmonic (6 MHz) 24 terms"}
+    outs = {}
+    for name, dtype in (("c64", torch.complex64), ("c128", torch.complex128)):
+        if name == "c128" and not fp64:
+            continue
+        p1 = tbs.Plan(c.grid, c.dx, tbs.background_k0(om, c.c0, c.alpha0, c.y), dtype=dtype).tabulate()
+        p2 = tbs.Plan(c.grid, c.dx, tbs.background_k0(2 * om, c.c0, c.alpha0, c.y), dtype=dtype).tabulate()
+        V1 = p1.potential(cd, om, c.c0, c.alpha0, c.y)
+        V2 = p2.potential(cd, 2 * om, c.c0, c.alpha0, c.y)
+        s = torch.from_numpy(c.sources).to(dev, dtype)
+        f1 = torch.empty_like(s)
+        S2 = torch.empty_like(s)
+        f2 = torch.empty_like(s)
+
+        def step():
+            p1.solve(s, V1, c.nterms, out=f1)
+            p1.harmonic_source(f1, cd, om, c.rho, c.BA, out=S2)
+            p2.solve(S2, V2, c.nterms, out=f2)
+
+        ms, _ = time_solves_fn(step, steps, warmup)
+        esz = 8 if name == "c64" else 16
+        nb = 2 * grid_step_bytes(c.grid, p1.padded, 1, esz, name == "c64", c.nterms)
+        gpt = 2 * c.points * c.nterms
+        log(f"[bench] harmonic3d {name}: {ms:.2f} ms/step")
+        outs[name] = (f1.cpu(), f2.cpu())
+        entry = {"value": gpt / (ms * 1e-3), "ms_per_step": ms, "alg_bytes_per_step": nb,
+                 "achieved_GBps": nb / (ms * 1e-3) / 1e9, "frac": nb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        if name == "c64":
+            res.update(entry)
+            res["unit"] = "grid-point·terms/s"
+        else:
+            res["fp64_plain"] = entry
+        p1.close()
+        p2.close()
+        del s, f1, S2, f2
+        torch.cuda.empty_cache()
+    if "c128" in outs:
+        for k, nm in ((0, "fundamental"), (1, "harmonic")):
+            a = outs["c64"][k].numpy().astype(np.complex128)
+            b = outs["c128"][k].numpy()
+            res[f"rel_l2_fp32_vs_fp64_{nm}"] = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+        res["speedup_fp32_vs_fp64"] = res["fp64_plain"]["ms_per_step"] / res["ms_per_step"]
+    return res
+
+
+def run_adjoint2d(dev, steps: int, warmup: int):
+    """One misfit gradient: 1024^2, 16 frequencies (2-6 MHz) x 8 sources, 128
+    receivers, 25 terms, FP32 adjoint through torch.autograd (forward series,
+    misfit, adjoint series paired with stored partial sums)."""
+    import torch
+    import workloads
+    import paper_2507_13754_amd as tbs
+    from paper_2507_13754_amd.autograd import MisfitProblem, TBSMisfit
+    prob = workloads.adjoint2d()
+    n = prob.grid[0]
+    rec = torch.from_numpy(prob.receivers[:, 0] * n + prob.receivers[:, 1]).to(dev)
+    src = torch.from_numpy(prob.sources).to(dev, torch.complex64)
+    ct = torch.from_numpy(prob.c_true).to(dev)
+    # observed data from the true map with the same library
+    p_obs = []
+    for f in prob.freqs:
+        om = 2 * math.pi * f
+        pl = tbs.Plan(prob.grid, prob.dx, tbs.background_k0(om, workloads.C0, prob.alpha0, prob.y),
+                      batch=src.shape[0]).tabulate()
+        p = pl.solve(src, pl.potential(ct, om, workloads.C0, prob.alpha0, prob.y), prob.nterms)
+        p_obs.append(p[:, prob.receivers[:, 0], prob.receivers[:, 1]].contiguous())
+        pl.close()
+    mp = MisfitProblem(prob.grid, prob.dx, prob.freqs, workloads.C0, prob.alpha0, prob.y, src, rec,
+                       p_obs, prob.nterms)
+    c = torch.from_numpy(prob.c_model).to(dev)
+
+    def step():
+        cc = c.clone().requires_grad_(True)
+        TBSMisfit.apply(cc, mp).backward()
+        return cc.grad
+
+    ms, _ = time_solves_fn(step, steps, warmup)
+    nsrc = src.shape[0]
+    P = n * n
+    # forward solve, adjoint's forward replay and adjoint series: 3 series of L terms
+    gpt = 3 * P * prob.nterms * nsrc * len(prob.freqs)
+    log(f"[bench] adjoint2d: {ms:.1f} ms per gradient")
+    mp.close()
+    return {"workload": "adjoint2d: 1024^2, 16 frequencies 2-6 MHz x 8 sources, 128 receivers, 25 terms, "
+                        "FP32 gradient via torch.autograd", "ms_per_gradient": ms,
+            "value": gpt / (ms * 1e-3), "unit": "grid-point·terms/s (3 series per (f, s))"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -160,6 +339,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
+    ap.add_argument("--extra", default="broadband,harmonic3d,adjoint2d",
+                    help="comma-separated side workloads reported in the same line ('' for none)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         log("bench.py measures one GPU: this build runs the hot path on a single MI355X "
@@ -273,6 +454,19 @@ def main():
         line["cpu_baseline"] = cpu_baseline(case, args.cpu_seconds)
     for r in res.values():
         r["plan"].close()
+    del res
+    torch.cuda.empty_cache()
+    extras = [e for e in args.extra.split(",") if e]
+    if extras:
+        line["side_workloads"] = {}
+    if "broadband" in extras:
+        line["side_workloads"]["broadband"] = run_broadband(
+            dev, max(2, args.steps // 5), 1, not args.no_fp64,
+            0.0 if args.no_cpu_baseline else min(args.cpu_seconds, 10.0))
+    if "harmonic3d" in extras:
+        line["side_workloads"]["harmonic3d"] = run_harmonic3d(dev, max(2, args.steps // 4), 1, not args.no_fp64)
+    if "adjoint2d" in extras:
+        line["side_workloads"]["adjoint2d"] = run_adjoint2d(dev, 2, 1)
     print(json.dumps(line), flush=True)
 
 

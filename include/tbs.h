@@ -186,6 +186,31 @@ int tbs_misfit(tbs_plan *plan, const void *p_dev, const int64_t *rec_dev, int nr
 int tbs_speed_gradient(tbs_plan *plan, const void *g_dev, const void *dVdc_dev,
                        double *grad_c_dev, int accumulate);
 
+/* ---- batches of plans (many grids, one graph launch) -------------------- */
+
+typedef struct tbs_batch tbs_batch;
+
+/* Group plans (e.g. one per frequency of a broadband pulse, each with its own
+ * grid, k0 and B right-hand sides) for joint solves.  All plans must be 2D,
+ * share the dtype and be tabulated; the batch queues its work on the first
+ * plan's stream.  The plans must outlive the batch.  Passes of grids whose
+ * padded lengths coincide run in one grouped kernel launch per term. */
+int tbs_batch_create(tbs_batch **out, tbs_plan *const *plans, int nplans);
+
+/* The L-term series of every plan in the batch (the tbs_solve contract per
+ * plan): sources[i], potentials[i] (non-NULL) and p_outs[i] are dev pointers
+ * for plan i.  The first call for a set of pointers and L records the whole
+ * sequence as a HIP graph; later calls with the same pointers replay it.
+ * residual_out: host double [sum_i B_i][L] (plan order) or NULL. */
+int tbs_batch_solve(tbs_batch *batch, const void *const *sources, const void *const *potentials,
+                    int nterms, void *const *p_outs, double *residual_out);
+
+/* Release the batch (not its plans; NULL-safe). */
+void tbs_batch_destroy(tbs_batch *batch);
+
+/* Message of the batch's last failure (NULL-safe). */
+const char *tbs_batch_last_error(const tbs_batch *batch);
+
 /* Per-pass device timing.  While enabled, every pass launch is bracketed by
  * two HIP events recorded on the plan's stream.  Pass kinds (index into the
  * output arrays): 0 first row pass (source in), 1 middle row passes,

@@ -33,7 +33,8 @@ EXPORTS = (
     "tbs_plan_set_stream", "tbs_green_tabulate", "tbs_green_import", "tbs_green_export",
     "tbs_potential", "tbs_solve", "tbs_harmonic_source", "tbs_adjoint", "tbs_misfit",
     "tbs_speed_gradient", "tbs_profile_enable", "tbs_profile_read", "tbs_plan_destroy",
-    "tbs_last_error",
+    "tbs_last_error", "tbs_batch_create", "tbs_batch_solve", "tbs_batch_destroy",
+    "tbs_batch_last_error",
 )
 PASS_KINDS = ("row_first", "row_mid", "row_last", "col_conv", "col_fwd", "col_inv")
 
@@ -91,6 +92,11 @@ def library() -> ctypes.CDLL:
         "tbs_profile_enable": (ctypes.c_int, [vp, ctypes.c_int]),
         "tbs_profile_read": (ctypes.c_int, [vp, dp, i64p]),
         "tbs_plan_destroy": (None, [vp]),
+        "tbs_batch_create": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int]),
+        "tbs_batch_solve": (ctypes.c_int, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int,
+                                           ctypes.POINTER(vp), dp]),
+        "tbs_batch_destroy": (None, [vp]),
+        "tbs_batch_last_error": (ctypes.c_char_p, [vp]),
         "tbs_last_error": (ctypes.c_char_p, [vp]),
     }
     for name, (res, args) in sig.items():
@@ -354,3 +360,58 @@ class Plan:
         _check(library().tbs_speed_gradient(self._h, gp, dp, op, int(accumulate)), self._h,
                "tbs_speed_gradient")
         return out
+
+
+class Batch:
+    """Several 2D plans solved together: passes of grids with equal padded
+    lengths share one grouped launch per term, and the whole series is recorded
+    once as a HIP graph and replayed for the same buffers."""
+
+    def __init__(self, plans: Sequence[Plan]):
+        L = library()
+        self.plans = list(plans)
+        arr = (ctypes.c_void_p * len(self.plans))(*[p._h for p in self.plans])
+        h = ctypes.c_void_p()
+        for p in self.plans:
+            p._sync_stream()
+        rc = L.tbs_batch_create(ctypes.byref(h), arr, len(self.plans))
+        if rc != TBS_OK:
+            raise TBSError(rc, f"tbs_batch_create: {L.tbs_last_error(None).decode()}")
+        self._h = h
+
+    def solve(self, sources, potentials, nterms: int, outs=None, residual: bool = False):
+        torch = _torch()
+        n = len(self.plans)
+        if len(sources) != n or len(potentials) != n:
+            raise ValueError("one source and one potential per plan")
+        if outs is None:
+            outs = [torch.empty((p.batch,) + p.shape, dtype=p.dtype, device=s.device)
+                    for p, s in zip(self.plans, sources)]
+        sp = [_ptr(s, p.dtype, (p.batch,) + p.shape, "source") for p, s in zip(self.plans, sources)]
+        vp = [_ptr(v, p.dtype, p.shape, "potential") for p, v in zip(self.plans, potentials)]
+        op = [_ptr(o, p.dtype, (p.batch,) + p.shape, "out") for p, o in zip(self.plans, outs)]
+        A = ctypes.c_void_p * n
+        rows = sum(p.batch for p in self.plans)
+        self.plans[0]._sync_stream()     # the caller's stream the batch joins
+        res = np.empty((rows, nterms), dtype=np.float64) if residual else None
+        L = library()
+        rc = L.tbs_batch_solve(self._h, A(*sp), A(*vp), int(nterms), A(*op),
+                               res.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if residual else None)
+        if rc < 0:
+            raise TBSError(rc, f"tbs_batch_solve: {L.tbs_batch_last_error(self._h).decode()}")
+        if rc > 0:
+            import warnings
+            warnings.warn(f"tbs_batch_solve: {L.tbs_status_string(rc).decode()}: "
+                          f"{L.tbs_batch_last_error(self._h).decode()}", TBSWarning, stacklevel=2)
+        return (outs, res) if residual else outs
+
+    def close(self):
+        if getattr(self, "_h", None):
+            library().tbs_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -206,10 +206,10 @@ int row_blocks(const tbs_plan* p) {
   return (int)((rows + NR - 1) / NR);
 }
 
-// Row pass of one term.
-int run_row(tbs_plan* p, int in_mode, int acc, int out_spec, bool adjoint, const void* src,
-            const void* V, void* pacc, void* pstore_slot, const void* pair, void* grad,
-            double* partials) {
+// Arguments of one row pass.
+tbs::RowArgs make_row_args(tbs_plan* p, int in_mode, int acc, int out_spec, bool adjoint,
+                           const void* src, const void* V, void* pacc, void* pstore_slot,
+                           const void* pair, void* grad, double* partials) {
   tbs::RowArgs a{};
   a.X = p->X;
   a.src = src;
@@ -232,9 +232,51 @@ int run_row(tbs_plan* p, int in_mode, int acc, int out_spec, bool adjoint, const
   a.pstore = pstore_slot;
   a.cb = p->cb;
   a.xcd_remap = 1;
+  return a;
+}
+
+// Row pass of one term.
+int run_row(tbs_plan* p, int in_mode, int acc, int out_spec, bool adjoint, const void* src,
+            const void* V, void* pacc, void* pstore_slot, const void* pair, void* grad,
+            double* partials) {
+  const tbs::RowArgs a = make_row_args(p, in_mode, acc, out_spec, adjoint, src, V, pacc,
+                                       pstore_slot, pair, grad, partials);
   ProfScope ps(p, in_mode == tbs::ROW_IN_SOURCE ? PK_ROW_FIRST : (out_spec ? PK_ROW_MID : PK_ROW_LAST));
   TBS_LAUNCH(p, tbs::launch_row_pass(p->fp64, (int)p->M[0], a, row_blocks(p), p->stream));
   return TBS_OK;
+}
+
+// Arguments of the 2D column convolution pass; *nc receives the columns per block.
+tbs::ColArgs make_conv2d_args(tbs_plan* p, bool adjoint, int* nc) {
+  const int64_t cb = p->cb;
+  const int64_t nkb = p->M[0] / cb;
+  tbs::ColArgs a{};
+  a.in = p->X;
+  a.out = p->X;
+  a.tw = p->tw[1];
+  a.ghat = p->ghat;
+  a.op = tbs::COL_CONV;
+  a.conj_g = adjoint ? 1 : 0;
+  a.n_in = (int)p->N[1];
+  a.n_out = (int)p->N[1];
+  a.in_astride = a.out_astride = cb;
+  a.in_rs = a.out_rs = nkb * p->N[1] * cb;
+  a.in_s1 = a.out_s1 = p->N[1] * cb;
+  a.in_s0 = a.out_s0 = 0;
+  *nc = tbs::conv_cols_per_block((int)p->M[1], p->fp64, (int)cb);
+  a.nrhs = p->batch;
+  a.sub = (int)cb / *nc;
+  a.n1 = (int)nkb * a.sub;
+  a.n0 = 1;
+  a.cb = (int)cb;
+  a.zcols = 0;
+  a.zlim = 1;
+  a.mx = (int)p->M[0];
+  a.mm = 1;
+  a.g_sx = p->M[1] / 2 + 1;
+  a.g_sm = 0;
+  a.xcd_remap = 1;
+  return a;
 }
 
 // Green's-function application to the row-pass output (all columns).
@@ -242,32 +284,8 @@ int run_cols(tbs_plan* p, bool adjoint) {
   const int64_t cb = p->cb;
   const int64_t nkb = p->M[0] / cb;
   if (p->ndim == 2) {
-    tbs::ColArgs a{};
-    a.in = p->X;
-    a.out = p->X;
-    a.tw = p->tw[1];
-    a.ghat = p->ghat;
-    a.op = tbs::COL_CONV;
-    a.conj_g = adjoint ? 1 : 0;
-    a.n_in = (int)p->N[1];
-    a.n_out = (int)p->N[1];
-    a.in_astride = a.out_astride = cb;
-    a.in_rs = a.out_rs = nkb * p->N[1] * cb;
-    a.in_s1 = a.out_s1 = p->N[1] * cb;
-    a.in_s0 = a.out_s0 = 0;
-    const int nc = tbs::conv_cols_per_block((int)p->M[1], p->fp64, (int)cb);
-    a.nrhs = p->batch;
-    a.sub = (int)cb / nc;
-    a.n1 = (int)nkb * a.sub;
-    a.n0 = 1;
-    a.cb = (int)cb;
-    a.zcols = 0;
-    a.zlim = 1;
-    a.mx = (int)p->M[0];
-    a.mm = 1;
-    a.g_sx = p->M[1] / 2 + 1;
-    a.g_sm = 0;
-    a.xcd_remap = 1;
+    int nc = 0;
+    const tbs::ColArgs a = make_conv2d_args(p, adjoint, &nc);
     ProfScope ps(p, PK_COL_CONV);
     TBS_LAUNCH(p, tbs::launch_col_pass(p->fp64, (int)p->M[1], nc, a, p->stream));
     return TBS_OK;
@@ -425,6 +443,85 @@ int check_plan_ready(tbs_plan* p) {
 
 }  // namespace
 
+// ------------------------------------------------------------- batches ----
+
+struct tbs_batch {
+  std::vector<tbs_plan*> plans;
+  hipStream_t stream = nullptr;   // the batch's own stream (graphs are recorded and run here)
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  bool fp64 = false;
+  struct Group {
+    int M = 0, cb = 4, nc = 0;
+    std::vector<int> members;  // plan indices
+    int first = 0;             // index of the first member in the descriptor order
+    int starts_off = 0;        // offset of this group's starts array
+    int total = 0;             // blocks of one grouped launch
+  };
+  std::vector<Group> rgroups, cgroups;
+  std::vector<int> rpos, cpos;   // plan -> position in the row / column descriptor order
+  // device tables
+  void* d_row = nullptr;         // RowArgs [L+1][nplans]
+  size_t d_row_bytes = 0;
+  void* d_col = nullptr;         // ColArgs [nplans]
+  void* d_starts = nullptr;      // int
+  size_t d_starts_bytes = 0;
+  // recorded graph and the arguments it was recorded for
+  hipGraphExec_t exec = nullptr;
+  std::vector<const void*> key;
+  int key_L = 0;
+  std::string err;
+};
+
+namespace {
+
+int bfail(tbs_batch* b, int code, const std::string& m) {
+  if (b) b->err = m;
+  return code;
+}
+
+void batch_free_tables(tbs_batch* b) {
+  if (b->d_row) (void)hipFree(b->d_row);
+  if (b->d_col) (void)hipFree(b->d_col);
+  if (b->d_starts) (void)hipFree(b->d_starts);
+  b->d_row = b->d_col = b->d_starts = nullptr;
+  b->d_row_bytes = b->d_starts_bytes = 0;
+}
+
+void batch_drop_graph(tbs_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  b->exec = nullptr;
+  b->key.clear();
+  b->key_L = 0;
+}
+
+// Enqueue the whole batched series (no synchronisation).
+int batch_enqueue(tbs_batch* b, int L) {
+  const int np = (int)b->plans.size();
+  const tbs::RowArgs* drow = (const tbs::RowArgs*)b->d_row;
+  const tbs::ColArgs* dcol = (const tbs::ColArgs*)b->d_col;
+  const int* dst = (const int*)b->d_starts;
+  for (int n = 0; n <= L; ++n) {
+    for (const auto& g : b->rgroups) {
+      int e = tbs::launch_row_group(b->fp64, g.M, g.cb, drow + (size_t)n * np + g.first,
+                                    dst + g.starts_off, (int)g.members.size(), g.total, b->stream);
+      if (e) return bfail(b, TBS_ERR_HIP, std::string("grouped row pass: ") + hipGetErrorString((hipError_t)e));
+    }
+    if (n == L) break;
+    for (const auto& g : b->cgroups) {
+      int e = tbs::launch_col_group(b->fp64, g.M, g.nc, dcol + g.first, dst + g.starts_off,
+                                    (int)g.members.size(), g.total, b->stream);
+      if (e) return bfail(b, TBS_ERR_HIP, std::string("grouped column pass: ") + hipGetErrorString((hipError_t)e));
+    }
+  }
+  for (tbs_plan* p : b->plans) {
+    int e = tbs::launch_finish_norms(p->partials, L, L, p->batch, row_blocks(p), p->resid, b->stream);
+    if (e) return bfail(b, TBS_ERR_HIP, std::string("norms: ") + hipGetErrorString((hipError_t)e));
+  }
+  return TBS_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int tbs_version(void) { return 100; }
@@ -446,9 +543,11 @@ const char* tbs_status_string(int s) {
 int tbs_padded_length(int64_t n, int padding, int64_t* m_out) {
   if (!m_out || n < 1 || padding < 2 || n > (int64_t)1 << 30) return TBS_ERR_INVALID;
   const int64_t need = padding * n - 1;
-  for (int64_t m = 16; m <= 4096; m *= 2) {
-    if (m >= need && tbs::fft_length_supported((int)m)) {
-      *m_out = m;
+  int lens[64];
+  const int nl = tbs::fft_supported_lengths(lens, 64);
+  for (int i = 0; i < nl; ++i) {
+    if (lens[i] >= need) {
+      *m_out = lens[i];
       return TBS_OK;
     }
   }
@@ -846,6 +945,216 @@ int tbs_profile_read(tbs_plan* p, double* ms, int64_t* cnt) {
   p->ev_used = 0;
   p->ev_marks.clear();
   return TBS_OK;
+}
+
+int tbs_batch_create(tbs_batch** out, tbs_plan* const* plans, int nplans) {
+  if (!out) return TBS_ERR_INVALID;
+  *out = nullptr;
+  if (!plans || nplans < 1) return fail(nullptr, TBS_ERR_INVALID, "empty batch");
+  tbs_batch* b = new (std::nothrow) tbs_batch();
+  if (!b) return fail(nullptr, TBS_ERR_OOM, "host allocation failed");
+  for (int i = 0; i < nplans; ++i) {
+    tbs_plan* p = plans[i];
+    if (!p || p->ndim != 2 || !p->green_ready || p->fp64 != plans[0]->fp64) {
+      delete b;
+      return fail(nullptr, TBS_ERR_INVALID,
+                  "batch plans must be 2D, tabulated and of one dtype");
+    }
+    b->plans.push_back(p);
+  }
+  b->fp64 = plans[0]->fp64;
+  // A graph can only be recorded on a created stream (not the null stream):
+  // the batch owns one (default priority) and joins the caller's stream with
+  // events around every replay.
+  if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    tbs_batch_destroy(b);
+    return fail(nullptr, TBS_ERR_HIP, "batch stream/events");
+  }
+  // group by padded length (rows: M_x; columns: M_y and the column shape)
+  b->rpos.assign(nplans, 0);
+  b->cpos.assign(nplans, 0);
+  auto find_or_add = [](std::vector<tbs_batch::Group>& gs, int M, int cb, int nc) -> tbs_batch::Group& {
+    for (auto& g : gs)
+      if (g.M == M && g.cb == cb && g.nc == nc) return g;
+    gs.push_back(tbs_batch::Group());
+    gs.back().M = M;
+    gs.back().cb = cb;
+    gs.back().nc = nc;
+    return gs.back();
+  };
+  for (int i = 0; i < nplans; ++i) {
+    tbs_plan* p = b->plans[i];
+    find_or_add(b->rgroups, (int)p->M[0], p->cb, 0).members.push_back(i);
+    int nc = 0;
+    (void)make_conv2d_args(p, false, &nc);
+    find_or_add(b->cgroups, (int)p->M[1], p->cb, nc).members.push_back(i);
+  }
+  std::vector<int> starts;
+  int pos = 0;
+  for (auto& g : b->rgroups) {
+    g.first = pos;
+    g.starts_off = (int)starts.size();
+    int acc = 0;
+    for (int i : g.members) {
+      b->rpos[i] = pos++;
+      starts.push_back(acc);
+      acc += row_blocks(b->plans[i]) * b->plans[i]->batch;
+    }
+    g.total = acc;
+  }
+  pos = 0;
+  for (auto& g : b->cgroups) {
+    g.first = pos;
+    g.starts_off = (int)starts.size();
+    int acc = 0;
+    for (int i : g.members) {
+      b->cpos[i] = pos++;
+      starts.push_back(acc);
+      int nc = 0;
+      const tbs::ColArgs c = make_conv2d_args(b->plans[i], false, &nc);
+      acc += c.nrhs * c.n1 * c.n0;
+    }
+    g.total = acc;
+  }
+  b->d_starts_bytes = starts.size() * sizeof(int);
+  if (hipMalloc(&b->d_starts, b->d_starts_bytes) != hipSuccess ||
+      hipMemcpy(b->d_starts, starts.data(), b->d_starts_bytes, hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipGetLastError();
+    batch_free_tables(b);
+    delete b;
+    return fail(nullptr, TBS_ERR_OOM, "batch tables");
+  }
+  *out = b;
+  return TBS_OK;
+}
+
+int tbs_batch_solve(tbs_batch* b, const void* const* sources, const void* const* potentials,
+                    int L, void* const* p_outs, double* residual_out) {
+  if (!b) return TBS_ERR_INVALID;
+  if (!sources || !potentials || !p_outs) return bfail(b, TBS_ERR_INVALID, "NULL pointer array");
+  if (L < 1 || L > 100000) return bfail(b, TBS_ERR_INVALID, "nterms must be >= 1");
+  const int np = (int)b->plans.size();
+  std::vector<const void*> key;
+  for (int i = 0; i < np; ++i) {
+    if (!sources[i] || !potentials[i] || !p_outs[i])
+      return bfail(b, TBS_ERR_INVALID, "batch solves need source, potential and output per plan");
+    key.push_back(sources[i]);
+    key.push_back(potentials[i]);
+    key.push_back(p_outs[i]);
+  }
+  for (tbs_plan* p : b->plans) key.push_back(p->ghat);
+  if (!(b->exec && key == b->key && L == b->key_L)) {
+    batch_drop_graph(b);
+    // per-plan scratch for L terms, then the descriptor tables
+    for (tbs_plan* p : b->plans) {
+      const size_t per_term = (size_t)2 * p->batch * row_blocks(p);
+      if (ensure_doubles(p, &p->partials, &p->partials_cap, per_term * (size_t)L) ||
+          ensure_doubles(p, &p->resid, &p->resid_cap, (size_t)p->batch * L))
+        return bfail(b, TBS_ERR_OOM, p->err);
+    }
+    std::vector<tbs::RowArgs> rows((size_t)(L + 1) * np);
+    std::vector<tbs::ColArgs> cols((size_t)np);
+    for (int i = 0; i < np; ++i) {
+      tbs_plan* p = b->plans[i];
+      const size_t per_term = (size_t)2 * p->batch * row_blocks(p);
+      for (int n = 0; n <= L; ++n) {
+        tbs::RowArgs r;
+        if (n == 0)
+          r = make_row_args(p, tbs::ROW_IN_SOURCE, tbs::ACC_NONE, 1, false, sources[i], nullptr,
+                            nullptr, nullptr, nullptr, nullptr, nullptr);
+        else
+          r = make_row_args(p, tbs::ROW_IN_SPECTRAL, n == 1 ? tbs::ACC_INIT : tbs::ACC_ADD,
+                            n < L ? 1 : 0, false, nullptr, potentials[i], p_outs[i], nullptr,
+                            nullptr, nullptr, p->partials + (size_t)(n - 1) * per_term);
+        rows[(size_t)n * np + b->rpos[i]] = r;
+      }
+      int nc = 0;
+      cols[b->cpos[i]] = make_conv2d_args(p, false, &nc);
+    }
+    const size_t rb = rows.size() * sizeof(tbs::RowArgs);
+    if (b->d_row_bytes < rb) {
+      if (b->d_row) (void)hipFree(b->d_row);
+      b->d_row = nullptr;
+      b->d_row_bytes = 0;
+      if (hipMalloc(&b->d_row, rb) != hipSuccess) {
+        (void)hipGetLastError();
+        return bfail(b, TBS_ERR_OOM, "batch descriptor table");
+      }
+      b->d_row_bytes = rb;
+    }
+    if (!b->d_col && hipMalloc(&b->d_col, cols.size() * sizeof(tbs::ColArgs)) != hipSuccess) {
+      (void)hipGetLastError();
+      b->d_col = nullptr;
+      return bfail(b, TBS_ERR_OOM, "batch descriptor table");
+    }
+    if (hipMemcpy(b->d_row, rows.data(), rb, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->d_col, cols.data(), cols.size() * sizeof(tbs::ColArgs), hipMemcpyHostToDevice) !=
+            hipSuccess)
+      return bfail(b, TBS_ERR_HIP, "descriptor upload failed");
+    // record the sequence as a graph
+    hipGraph_t graph = nullptr;
+    if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      (void)hipGetLastError();
+      return bfail(b, TBS_ERR_HIP, "graph capture could not start");
+    }
+    int rc = batch_enqueue(b, L);
+    hipError_t e = hipStreamEndCapture(b->stream, &graph);
+    if (rc) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    if (e != hipSuccess) return bfail(b, TBS_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      b->exec = nullptr;
+      return bfail(b, TBS_ERR_HIP, std::string("graph instantiation: ") + hipGetErrorString(e));
+    }
+    b->key = key;
+    b->key_L = L;
+  }
+  // caller's stream -> batch stream -> caller's stream
+  const hipStream_t caller = b->plans[0]->stream;
+  hipError_t e = hipEventRecord(b->ev_in, caller);
+  if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->ev_in, 0);
+  if (e == hipSuccess) e = hipGraphLaunch(b->exec, b->stream);
+  if (e == hipSuccess) e = hipEventRecord(b->ev_out, b->stream);
+  if (e == hipSuccess) e = hipStreamWaitEvent(caller, b->ev_out, 0);
+  if (e != hipSuccess) return bfail(b, TBS_ERR_HIP, std::string("graph launch: ") + hipGetErrorString(e));
+  if (!residual_out) return TBS_OK;
+  e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return bfail(b, TBS_ERR_HIP, std::string("batch: ") + hipGetErrorString(e));
+  int warn = TBS_OK;
+  size_t off = 0;
+  for (tbs_plan* p : b->plans) {
+    int rc = check_residuals(p, residual_out + off, L);
+    if (rc < 0) return bfail(b, rc, p->err);
+    if (rc > 0 && warn == TBS_OK) {
+      warn = rc;
+      b->err = p->err;
+    }
+    off += (size_t)p->batch * L;
+  }
+  return warn;
+}
+
+void tbs_batch_destroy(tbs_batch* b) {
+  if (!b) return;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  batch_drop_graph(b);
+  batch_free_tables(b);
+  if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+  if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+  if (b->stream) (void)hipStreamDestroy(b->stream);
+  delete b;
+}
+
+const char* tbs_batch_last_error(const tbs_batch* b) {
+  if (!b) return g_create_err.c_str();
+  return b->err.c_str();
 }
 
 const char* tbs_last_error(const tbs_plan* p) {

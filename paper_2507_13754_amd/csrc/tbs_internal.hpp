@@ -55,8 +55,38 @@ struct ColArgs {
 };
 enum ColOp { COL_CONV = 0, COL_FWD = 1, COL_INV = 2, COL_FULL = 3 };
 
+// FFT lengths with compiled kernels: powers of two, 3 * 2^a and 5 * 2^a.
+#define TBS_LENGTHS_POW2(X) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)
+#define TBS_LENGTHS_THREE(X) X(48) X(96) X(192) X(384) X(768) X(1536) X(3072)
+#define TBS_LENGTHS_FIVE(X) X(80) X(160) X(320) X(640) X(1280) X(2560)
+
+enum PassKind { PASS_ROW = 0, PASS_COL = 1, PASS_ROW_FULL = 2, PASS_ROW_GROUP = 3, PASS_COL_GROUP = 4 };
+
+// One launch request for the length-family dispatchers.
+struct PassReq {
+  int kind = PASS_ROW;
+  bool fp64 = false;
+  int M = 0;
+  int nc = 0;                       // columns per block (column passes)
+  int cb = 4;                       // layout block width (grouped row passes)
+  const RowArgs* row = nullptr;     // PASS_ROW
+  int nblk_rows = 0;
+  const ColArgs* col = nullptr;     // PASS_COL
+  void* data = nullptr;             // PASS_ROW_FULL
+  const void* tw = nullptr;
+  int nrows = 0, inverse = 0;
+  const RowArgs* row_descs = nullptr;  // grouped: device arrays
+  const ColArgs* col_descs = nullptr;
+  const int* starts = nullptr;
+  int ngroups = 0, total = 0;
+};
+int dispatch_pow2(const PassReq& q, hipStream_t s);
+int dispatch_three(const PassReq& q, hipStream_t s);
+int dispatch_five(const PassReq& q, hipStream_t s);
+
 // Lengths the library has kernels for.
 bool fft_length_supported(int M);
+int fft_supported_lengths(int* out, int cap);   // ascending
 int fft_elems_per_thread(int M, bool fp64);
 int row_rows_per_block(int M, bool fp64);
 int spectral_block(int My, bool fp64);
@@ -66,6 +96,11 @@ int conv_cols_per_block(int M, bool fp64, int cb);  // columns per convolution b
 int launch_row_pass(bool fp64, int M, const RowArgs& a, int nblk_rows, hipStream_t s);
 int launch_col_pass(bool fp64, int M, int NC, const ColArgs& a, hipStream_t s);
 int launch_row_fft_full(int M, void* data, const void* tw, int nrows, int inverse, hipStream_t s);
+// Grouped launches (descs/starts are device arrays of ngroups entries).
+int launch_row_group(bool fp64, int M, int cb, const RowArgs* descs, const int* starts, int ngroups,
+                     int total_blocks, hipStream_t s);
+int launch_col_group(bool fp64, int M, int nc, const ColArgs* descs, const int* starts, int ngroups,
+                     int total_blocks, hipStream_t s);
 
 // Elementwise / reduction kernels.
 int launch_finish_norms(const double* partials, int nterms, int nvalid, int nrhs, int nblk,

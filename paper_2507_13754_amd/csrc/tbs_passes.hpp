@@ -15,6 +15,8 @@
 // LDS is used only for the exchanges between radix stages.  Lines are read
 // and written in contiguous kBlock-wide column blocks so that every HBM access
 // is a full, coalesced segment.
+#pragma once
+
 #include <type_traits>
 
 #include "tbs_fft.hpp"
@@ -78,7 +80,7 @@ __device__ __forceinline__ int fold(int k, int m) { return k <= (m >> 1) ? k : m
 // ---------------------------------------------------------------- row pass --
 
 template <typename T, int M, int E, int NR, int CB, bool SPLIT>
-__global__ void __launch_bounds__(NR * (M / E), (M >= 2048 ? TBS_MIN_WAVES : 0)) k_row_pass(RowArgs a) {
+__device__ __forceinline__ void row_pass_body(const RowArgs& a, const int lb) {
   constexpr int TPT = M / E;
   constexpr int NKB = M / CB;
   constexpr int LD = lds_len(M);
@@ -95,7 +97,6 @@ __global__ void __launch_bounds__(NR * (M / E), (M >= 2048 ? TBS_MIN_WAVES : 0))
   const int r = (tid / CB) % NR;
   const int thi = tid / (CB * NR);
   const int t = thi * CB + tlo;
-  const int lb = xcd_block(blockIdx.x, gridDim.x, a.xcd_remap);
   const int rhs = lb % a.nrhs;
   const int rb = lb / a.nrhs;
   const int nblk = (a.nrows + NR - 1) / NR;
@@ -210,7 +211,7 @@ __global__ void __launch_bounds__(NR * (M / E), (M >= 2048 ? TBS_MIN_WAVES : 0))
 // ------------------------------------------------------------- column pass --
 
 template <typename T, int M, int E, int NC, int OP, bool SPLIT>
-__global__ void __launch_bounds__(NC * (M / E), (M >= 2048 ? TBS_MIN_WAVES : 0)) k_col_pass(ColArgs a) {
+__device__ __forceinline__ void col_pass_body(const ColArgs& a, const int lb) {
   constexpr int TPT = M / E;
   constexpr int LD = lds_len(M);
   constexpr bool HALF_IN = (OP == COL_CONV || OP == COL_FWD);
@@ -221,7 +222,6 @@ __global__ void __launch_bounds__(NC * (M / E), (M >= 2048 ? TBS_MIN_WAVES : 0))
   const int tid = threadIdx.x;
   const int col = tid % NC;
   const int tt = tid / NC;
-  const int lb = xcd_block(blockIdx.x, gridDim.x, a.xcd_remap);
   const int rhs = lb % a.nrhs;
   const int rest = lb / a.nrhs;
   const int i0 = rest % a.n0;
@@ -292,44 +292,74 @@ __global__ void __launch_bounds__(NR * (M / E)) k_row_fft_full(cx<T>* data, cons
   }
 }
 
-// ----------------------------------------------------------- dispatching --
+// ---------------------------------------------------------------- kernels --
 
-// Lengths with compiled kernels (powers of two; every one is 5-smooth).
-#define TBS_FOR_EACH_LENGTH(X) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)
-
-bool fft_length_supported(int M) {
-  switch (M) {
-#define TBS_CASE(m) case m:
-    TBS_FOR_EACH_LENGTH(TBS_CASE)
-#undef TBS_CASE
-    return true;
-    default:
-      return false;
-  }
+template <typename T, int M, int E, int NR, int CB, bool SPLIT>
+__global__ void __launch_bounds__(NR * (M / E)) k_row_pass(RowArgs a) {
+  row_pass_body<T, M, E, NR, CB, SPLIT>(a, xcd_block(blockIdx.x, gridDim.x, a.xcd_remap));
 }
 
-// Values per thread: more for long FP32 lines (more independent work per
-// thread, fewer threads), 16 for long FP64 lines (register budget).
+template <typename T, int M, int E, int NC, int OP, bool SPLIT>
+__global__ void __launch_bounds__(NC * (M / E)) k_col_pass(ColArgs a) {
+  col_pass_body<T, M, E, NC, OP, SPLIT>(a, xcd_block(blockIdx.x, gridDim.x, a.xcd_remap));
+}
+
+// Grouped launches: one kernel for several grids with the same line length.
+// Grid g owns blocks [starts[g], starts[g+1]); its arguments are descs[g].
+__device__ __forceinline__ int group_of(const int* __restrict__ starts, int ngroups, int b) {
+  int g = 0;
+  while (g + 1 < ngroups && starts[g + 1] <= b) ++g;
+  return g;
+}
+
+template <typename T, int M, int E, int NR, int CB, bool SPLIT>
+__global__ void __launch_bounds__(NR * (M / E)) k_row_pass_group(const RowArgs* __restrict__ descs,
+                                                                 const int* __restrict__ starts,
+                                                                 int ngroups) {
+  const int b = xcd_block(blockIdx.x, gridDim.x, 1);
+  const int g = group_of(starts, ngroups, b);
+  row_pass_body<T, M, E, NR, CB, SPLIT>(descs[g], b - starts[g]);
+}
+
+template <typename T, int M, int E, int NC, int OP, bool SPLIT>
+__global__ void __launch_bounds__(NC * (M / E)) k_col_pass_group(const ColArgs* __restrict__ descs,
+                                                                 const int* __restrict__ starts,
+                                                                 int ngroups) {
+  const int b = xcd_block(blockIdx.x, gridDim.x, 1);
+  const int g = group_of(starts, ngroups, b);
+  col_pass_body<T, M, E, NC, OP, SPLIT>(descs[g], b - starts[g]);
+}
+
+// ------------------------------------------------------- configurations ---
+
+// Odd part of a length (1, 3 or 5 for the compiled families).
+constexpr int odd_part(int M) {
+  while (M % 2 == 0) M /= 2;
+  return M;
+}
+
+// Values per thread.  Powers of two: 4 / 8 / 16 by length (FP32 lines of
+// 2048+ use TBS_E_LONG_F32).  3 * 2^a and 5 * 2^a: 8 * odd part for FP32
+// lines of 384+ / 640+ (radix-8 stages then one odd stage), else 4 * odd part.
 constexpr int elems_per_thread(int M, bool fp64) {
-  return M <= 64 ? 4 : (M <= 512 ? 8 : ((M <= 1024 || fp64) ? 16 : TBS_E_LONG_F32));
+  const int r = odd_part(M);
+  if (r == 1) return M <= 64 ? 4 : (M <= 512 ? 8 : ((M <= 1024 || fp64) ? 16 : TBS_E_LONG_F32));
+  if (!fp64 && ((r == 3 && M >= 384) || (r == 5 && M >= 640))) return 8 * r;
+  return 4 * r;
 }
-int fft_elems_per_thread(int M, bool fp64) { return elems_per_thread(M, fp64); }
-// Long lines exchange real and imaginary parts separately (half the LDS).
 constexpr bool split_lds(int M) { return M >= TBS_SPLIT_MIN; }
-
-// Rows per row-pass block: LDS (160 KB per CU) holds NR lines.
 constexpr int rows_per_block(int M, bool fp64) {
   return fp64 ? (M >= 4096 ? TBS_NR_F64 : (M >= 2048 && !split_lds(M) ? 2 : 4))
               : (M >= 2048 ? TBS_NR_F32 : 4);
 }
-int row_rows_per_block(int M, bool fp64) { return rows_per_block(M, fp64); }
+constexpr bool col_fits(int M, int NC, int esz) {
+  return (long)NC * lds_len(M) * (split_lds(M) ? esz / 2 : esz) <= 160L * 1024;
+}
 
-// Contiguous spectral columns per block of the intermediate layout: 4, except
-// FP64 with columns of 4096+ values (two such lines per block fit LDS twice).
-int spectral_block(int My, bool fp64) { return (fp64 && My >= 4096) ? 2 : 4; }
+// ------------------------------------------------------ launch templates --
 
 template <typename T, int M>
-static int row_launch(const RowArgs& a, int nblk_rows, hipStream_t s) {
+int row_launch(const RowArgs& a, int nblk_rows, hipStream_t s) {
   constexpr bool F64 = sizeof(T) == 8;
   constexpr int E = elems_per_thread(M, F64);
   constexpr int NR = rows_per_block(M, F64);
@@ -345,20 +375,27 @@ static int row_launch(const RowArgs& a, int nblk_rows, hipStream_t s) {
   return (int)hipGetLastError();
 }
 
-int launch_row_pass(bool fp64, int M, const RowArgs& a, int nblk_rows, hipStream_t s) {
-  switch (M) {
-#define TBS_CASE(m) \
-  case m:           \
-    return fp64 ? row_launch<double, m>(a, nblk_rows, s) : row_launch<float, m>(a, nblk_rows, s);
-    TBS_FOR_EACH_LENGTH(TBS_CASE)
-#undef TBS_CASE
-    default:
-      return (int)hipErrorInvalidValue;
+template <typename T, int M>
+int row_group_launch(const RowArgs* descs, const int* starts, int ngroups, int total, int cb,
+                     hipStream_t s) {
+  constexpr bool F64 = sizeof(T) == 8;
+  constexpr int E = elems_per_thread(M, F64);
+  constexpr int NR = rows_per_block(M, F64);
+  constexpr bool SP = split_lds(M);
+  if (cb == 4) {
+    hipLaunchKernelGGL((k_row_pass_group<T, M, E, NR, 4, SP>), dim3(total), dim3(NR * (M / E)), 0, s,
+                       descs, starts, ngroups);
+  } else if (cb == 2) {
+    hipLaunchKernelGGL((k_row_pass_group<T, M, E, NR, 2, SP>), dim3(total), dim3(NR * (M / E)), 0, s,
+                       descs, starts, ngroups);
+  } else {
+    return (int)hipErrorInvalidValue;
   }
+  return (int)hipGetLastError();
 }
 
 template <typename T, int M, int NC>
-static int col_launch(const ColArgs& a, hipStream_t s) {
+int col_launch(const ColArgs& a, hipStream_t s) {
   constexpr int E = elems_per_thread(M, sizeof(T) == 8);
   constexpr bool SP = split_lds(M);
   const int grid = a.nrhs * a.n1 * a.n0;
@@ -383,21 +420,8 @@ static int col_launch(const ColArgs& a, hipStream_t s) {
   return (int)hipGetLastError();
 }
 
-constexpr bool col_fits(int M, int NC, int esz) {
-  return (long)NC * lds_len(M) * (split_lds(M) ? esz / 2 : esz) <= 160L * 1024;
-}
-int conv_cols_per_block(int M, bool fp64, int cb) {
-  const int want = M >= 2048 ? (fp64 ? TBS_NC_F64 : TBS_NC_F32) : cb;
-  return want < cb ? want : cb;
-}
-
-int col_max_cols(int M, bool fp64) {
-  const int esz = fp64 ? 16 : 8;
-  return col_fits(M, 4, esz) ? 4 : (col_fits(M, 2, esz) ? 2 : 1);
-}
-
 template <typename T, int M>
-static int col_launch_nc(int NC, const ColArgs& a, hipStream_t s) {
+int col_launch_nc(int NC, const ColArgs& a, hipStream_t s) {
   constexpr int esz = (int)sizeof(cx<T>);
   if constexpr (col_fits(M, 4, esz)) {
     if (NC == 4) return col_launch<T, M, 4>(a, s);
@@ -414,20 +438,32 @@ static int col_launch_nc(int NC, const ColArgs& a, hipStream_t s) {
   return (int)hipErrorInvalidValue;
 }
 
-int launch_col_pass(bool fp64, int M, int NC, const ColArgs& a, hipStream_t s) {
-  switch (M) {
-#define TBS_CASE(m) \
-  case m:           \
-    return fp64 ? col_launch_nc<double, m>(NC, a, s) : col_launch_nc<float, m>(NC, a, s);
-    TBS_FOR_EACH_LENGTH(TBS_CASE)
-#undef TBS_CASE
-    default:
-      return (int)hipErrorInvalidValue;
+// Grouped convolution passes (2D column convolution only).
+template <typename T, int M>
+int col_group_launch(int NC, const ColArgs* descs, const int* starts, int ngroups, int total,
+                     hipStream_t s) {
+  constexpr int E = elems_per_thread(M, sizeof(T) == 8);
+  constexpr bool SP = split_lds(M);
+  constexpr int esz = (int)sizeof(cx<T>);
+  if constexpr (col_fits(M, 4, esz)) {
+    if (NC == 4) {
+      hipLaunchKernelGGL((k_col_pass_group<T, M, E, 4, COL_CONV, SP>), dim3(total), dim3(4 * (M / E)),
+                         0, s, descs, starts, ngroups);
+      return (int)hipGetLastError();
+    }
   }
+  if constexpr (col_fits(M, 2, esz)) {
+    if (NC == 2) {
+      hipLaunchKernelGGL((k_col_pass_group<T, M, E, 2, COL_CONV, SP>), dim3(total), dim3(2 * (M / E)),
+                         0, s, descs, starts, ngroups);
+      return (int)hipGetLastError();
+    }
+  }
+  return (int)hipErrorInvalidValue;
 }
 
 template <int M>
-static int rowfull_launch(void* data, const void* tw, int nrows, int inverse, hipStream_t s) {
+int rowfull_launch(void* data, const void* tw, int nrows, int inverse, hipStream_t s) {
   constexpr int E = elems_per_thread(M, true);
   constexpr int NR = rows_per_block(M, true);
   hipLaunchKernelGGL((k_row_fft_full<double, M, E, NR, split_lds(M)>), dim3((nrows + NR - 1) / NR),
@@ -436,16 +472,35 @@ static int rowfull_launch(void* data, const void* tw, int nrows, int inverse, hi
   return (int)hipGetLastError();
 }
 
-int launch_row_fft_full(int M, void* data, const void* tw, int nrows, int inverse, hipStream_t s) {
-  switch (M) {
-#define TBS_CASE(m) \
-  case m:           \
-    return rowfull_launch<m>(data, tw, nrows, inverse, s);
-    TBS_FOR_EACH_LENGTH(TBS_CASE)
-#undef TBS_CASE
-    default:
-      return (int)hipErrorInvalidValue;
+// One family of lengths: dispatches every launch kind for the lengths of its
+// list; returns hipErrorInvalidValue for a length it does not hold.
+#define TBS_FAMILY_DISPATCH(NAME, LIST)                                                          \
+  int NAME(const PassReq& q, hipStream_t s) {                                                    \
+    switch (q.M) {                                                                               \
+      LIST(TBS_FAMILY_CASE)                                                                       \
+      default:                                                                                    \
+        return (int)hipErrorInvalidValue;                                                         \
+    }                                                                                             \
   }
-}
+#define TBS_FAMILY_CASE(m)                                                                        \
+  case m:                                                                                         \
+    switch (q.kind) {                                                                             \
+      case PASS_ROW:                                                                              \
+        return q.fp64 ? row_launch<double, m>(*q.row, q.nblk_rows, s)                             \
+                      : row_launch<float, m>(*q.row, q.nblk_rows, s);                             \
+      case PASS_COL:                                                                              \
+        return q.fp64 ? col_launch_nc<double, m>(q.nc, *q.col, s)                                 \
+                      : col_launch_nc<float, m>(q.nc, *q.col, s);                                 \
+      case PASS_ROW_FULL:                                                                         \
+        return rowfull_launch<m>(q.data, q.tw, q.nrows, q.inverse, s);                            \
+      case PASS_ROW_GROUP:                                                                        \
+        return q.fp64 ? row_group_launch<double, m>(q.row_descs, q.starts, q.ngroups, q.total, q.cb, s) \
+                      : row_group_launch<float, m>(q.row_descs, q.starts, q.ngroups, q.total, q.cb, s); \
+      case PASS_COL_GROUP:                                                                        \
+        return q.fp64 ? col_group_launch<double, m>(q.nc, q.col_descs, q.starts, q.ngroups, q.total, s) \
+                      : col_group_launch<float, m>(q.nc, q.col_descs, q.starts, q.ngroups, q.total, s); \
+      default:                                                                                    \
+        return (int)hipErrorInvalidValue;                                                         \
+    }
 
 }  // namespace tbs

@@ -1,0 +1,109 @@
+"""Batched multi-grid solves (grouped launches + recorded graph) against the
+oracle and against single-plan solves; mixed-radix padded lengths."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {"c128": 1e-12, "c64": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def tdt(name):
+    return torch.complex128 if name == "c128" else torch.complex64
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+
+
+# frequency indices whose 1.2 cm grids pad to 3*2^a, 5*2^a and 2^a lengths,
+# two of them sharing a length (one grouped launch)
+FREQS = [0, 9, 20, 30, 31, 47]
+
+
+def cases(nangles=3, nterms=6):
+    return [workloads.broadband(i, nangles=nangles, nterms=nterms, extent=0.012) for i in FREQS]
+
+
+def build(dev, cs, dt):
+    import paper_2507_13754_amd as tbs
+    plans, srcs, pots = [], [], []
+    for c in cs:
+        k0 = tbs.background_k0(c.omega, c.c0, c.alpha0, c.y)
+        p = tbs.Plan(c.grid, c.dx, k0, dtype=tdt(dt), batch=c.sources.shape[0]).tabulate()
+        plans.append(p)
+        srcs.append(torch.from_numpy(c.sources).to(dev, tdt(dt)))
+        pots.append(p.potential(torch.from_numpy(c.c).to(dev), c.omega, c.c0, c.alpha0, c.y))
+    return plans, srcs, pots
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_batch_matches_oracle(dev, dt):
+    import paper_2507_13754_amd as tbs
+    cs = cases()
+    plans, srcs, pots = build(dev, cs, dt)
+    lengths = sorted({p.padded[0] for p in plans})
+    odd = {m // (m & -m) for m in lengths}
+    assert odd >= {1, 3, 5} and len(lengths) < len(plans)   # all families, one shared length
+    batch = tbs.Batch(plans)
+    outs, res = batch.solve(srcs, pots, cs[0].nterms, residual=True)
+    row = 0
+    for c, o in zip(cs, outs):
+        k0 = oracle.background_k0(c.omega, c.c0, c.alpha0, c.y)
+        V = oracle.potential(c.c, c.omega, c.c0, c.alpha0, c.y)
+        p_ref, r_ref = oracle.solve(k0, c.dx, c.sources, V, c.nterms)
+        got = o.cpu().numpy().astype(np.complex128)
+        err = max(rel(got[b], p_ref[b]) for b in range(got.shape[0]))
+        assert err <= TOL[dt], (c.name, err)
+        assert np.allclose(res[row:row + got.shape[0]], r_ref, rtol=1e-9 if dt == "c128" else 1e-3)
+        row += got.shape[0]
+    batch.close()
+
+
+def test_batch_equals_single_plan_solves_and_replays(dev):
+    import paper_2507_13754_amd as tbs
+    cs = cases(nangles=2, nterms=5)
+    plans, srcs, pots = build(dev, cs, "c64")
+    batch = tbs.Batch(plans)
+    outs = batch.solve(srcs, pots, 5)
+    first = [o.clone() for o in outs]
+    for p, s, v, o in zip(plans, srcs, pots, first):
+        single = p.solve(s, v, 5)
+        assert torch.equal(single, o)
+    # replay of the recorded graph with the same buffers
+    outs2 = batch.solve(srcs, pots, 5, outs=outs)
+    for a, b in zip(first, outs2):
+        assert torch.equal(a, b)
+    # new contents in the same buffers: the replay reads them
+    for s in srcs:
+        s.mul_(2.0)
+    outs3 = batch.solve(srcs, pots, 5, outs=outs)
+    for a, b in zip(first, outs3):
+        assert torch.allclose(b, 2.0 * a, rtol=1e-6, atol=0)
+    batch.close()
+
+
+def test_full_size_smallest_broadband_grid(dev):
+    """The 2 MHz grid of the broadband workload at full size (312^2, 16 angles,
+    25 terms, padded 640) in FP32 against the oracle."""
+    import paper_2507_13754_amd as tbs
+    c = workloads.broadband(0)
+    plans, srcs, pots = build(dev, [c], "c64")
+    assert plans[0].padded[0] == 640
+    outs = tbs.Batch(plans).solve(srcs, pots, c.nterms)
+    k0 = oracle.background_k0(c.omega, c.c0, c.alpha0, c.y)
+    V = oracle.potential(c.c, c.omega, c.c0, c.alpha0, c.y)
+    p_ref, _ = oracle.solve(k0, c.dx, c.sources, V, c.nterms)
+    got = outs[0].cpu().numpy().astype(np.complex128)
+    assert max(rel(got[b], p_ref[b]) for b in range(16)) <= TOL["c64"]

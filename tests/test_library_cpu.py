@@ -28,7 +28,8 @@ def test_library_exports_every_header_symbol():
 
 
 @pytest.mark.parametrize("n,pad,m", [(1, 2, 16), (8, 2, 16), (9, 2, 32), (256, 2, 512),
-                                     (2048, 2, 4096), (37, 2, 128), (100, 3, 512)])
+                                     (2048, 2, 4096), (37, 2, 80), (100, 3, 320), (300, 2, 640),
+                                     (380, 2, 768), (1247, 2, 2560), (1100, 2, 2560), (1500, 2, 3072)])
 def test_padded_length(n, pad, m):
     got = tbs.padded_length(n, pad)
     assert got == m and got >= pad * n - 1 and got % 2 == 0
