@@ -156,7 +156,7 @@ def grid_step_bytes(grid, padded, B, esz, kahan, L):
     return step_bytes(len(grid), N, M, B, esz, kahan, g, L)
 
 
-def run_broadband(dev, steps: int, warmup: int, fp64: bool, cpu_seconds: float):
+def run_broadband(dev, steps: int, warmup: int, fp64: bool, cpu_seconds: float, tune: bool = True):
     """48 frequencies (2-8 MHz) on their own lambda/6 grids over 4 x 4 cm, 16
     steering angles each, 25 terms: one batch, replayed as one graph."""
     import torch
@@ -172,6 +172,8 @@ def run_broadband(dev, steps: int, warmup: int, fp64: bool, cpu_seconds: float):
             c = workloads.broadband(i)
             k0 = tbs.background_k0(c.omega, c.c0, c.alpha0, c.y)
             p = tbs.Plan(c.grid, c.dx, k0, dtype=dtype, batch=c.sources.shape[0]).tabulate()
+            if tune:
+                p.autotune()
             plans.append(p)
             srcs.append(torch.from_numpy(c.sources).to(dev, dtype))
             pots.append(p.potential(torch.from_numpy(c.c).to(dev), c.omega, c.c0, c.alpha0, c.y))
@@ -337,6 +339,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="skip the block-shape autotuner")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
     ap.add_argument("--extra", default="broadband,harmonic3d,adjoint2d",
@@ -366,6 +369,7 @@ def main():
         t0 = time.perf_counter()
         plan = tbs.Plan(case.grid, case.dx, k0, dtype=dtype, batch=B).tabulate()
         t_tab = time.perf_counter() - t0
+        shapes = plan.autotune() if not args.no_tune else None
         V = plan.potential(c_dev, case.omega, case.c0, case.alpha0, case.y)
         s = torch.from_numpy(case.sources).to(dev, dtype)
         out = torch.empty((B,) + case.grid, dtype=dtype, device=dev)
@@ -376,7 +380,7 @@ def main():
         prof = profile_passes(plan, s, V, L, out, prof_steps)
         _, r = plan.solve(s, V, L, out=out, residual=True)
         res[name] = dict(plan=plan, out=out.clone(), ms=ms_ev, ms_wall=ms_wall, prof=prof,
-                         t_tab=t_tab, steps=steps, prof_steps=prof_steps, resid=r)
+                         t_tab=t_tab, steps=steps, prof_steps=prof_steps, resid=r, shapes=shapes)
         if args.calib_copy and name == "c64":
             a = torch.empty(256 * 1024 * 1024 // 4, dtype=torch.float32, device=dev).fill_(1.0)
             bb = torch.empty_like(a)
@@ -435,6 +439,7 @@ def main():
         "passes": passes32,
         "ms_per_step_wall": r32["ms_wall"],
         "tabulation_s": r32["t_tab"],
+        "autotuned_block_shapes": r32["shapes"],
         "residual_last": float(np.max(r32["resid"][:, -1])),
     }
     if "c128" in res:
@@ -462,7 +467,7 @@ def main():
     if "broadband" in extras:
         line["side_workloads"]["broadband"] = run_broadband(
             dev, max(2, args.steps // 5), 1, not args.no_fp64,
-            0.0 if args.no_cpu_baseline else min(args.cpu_seconds, 10.0))
+            0.0 if args.no_cpu_baseline else min(args.cpu_seconds, 10.0), not args.no_tune)
     if "harmonic3d" in extras:
         line["side_workloads"]["harmonic3d"] = run_harmonic3d(dev, max(2, args.steps // 4), 1, not args.no_fp64)
     if "adjoint2d" in extras:

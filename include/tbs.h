@@ -118,6 +118,17 @@ int tbs_plan_info(const tbs_plan *plan, int64_t padded_out[3], int64_t *device_b
 /* Queue later work on another stream. */
 int tbs_plan_set_stream(tbs_plan *plan, void *hip_stream);
 
+/* Autotuner: time the block-shape candidates of the row and column passes
+ * (rows per row-pass block, columns per convolution block) on this plan's
+ * shapes and keep the fastest.  The choice never changes the field arithmetic
+ * (p_out is bitwise identical; the FP64 residual norms are summed in another
+ * grouping and may differ in the last bits); it is cached per (device, grid, padded
+ * lengths, batch, dtype) for the life of the process.  2D plans only (3D plans
+ * keep the defaults).  Needs the spectrum (call after tbs_green_tabulate);
+ * clobbers the plan's intermediate buffers; synchronous.  Outputs (may be
+ * NULL): the chosen rows and columns per block. */
+int tbs_plan_autotune(tbs_plan *plan, int *row_nr_out, int *conv_nc_out);
+
 /* Tabulate the Green spectrum in FP64 on the device: W(m) = dx^d g(k0,|m|dx)
  * on the padded grid (W(0) = tbs_self_cell), forward FFT, scale 1/prod(M),
  * fold to the [0, M_x/2] x [0, M_y/2] (x [0, M_z/2]) table, round to the plan

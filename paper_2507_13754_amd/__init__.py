@@ -34,7 +34,7 @@ EXPORTS = (
     "tbs_potential", "tbs_solve", "tbs_harmonic_source", "tbs_adjoint", "tbs_misfit",
     "tbs_speed_gradient", "tbs_profile_enable", "tbs_profile_read", "tbs_plan_destroy",
     "tbs_last_error", "tbs_batch_create", "tbs_batch_solve", "tbs_batch_destroy",
-    "tbs_batch_last_error",
+    "tbs_batch_last_error", "tbs_plan_autotune",
 )
 PASS_KINDS = ("row_first", "row_mid", "row_last", "col_conv", "col_fwd", "col_inv")
 
@@ -89,6 +89,7 @@ def library() -> ctypes.CDLL:
         "tbs_adjoint": (ctypes.c_int, [vp, vp, vp, ctypes.c_int, vp, vp, dp, ctypes.c_int]),
         "tbs_misfit": (ctypes.c_int, [vp, vp, vp, ctypes.c_int, vp, vp, vp]),
         "tbs_speed_gradient": (ctypes.c_int, [vp, vp, vp, vp, ctypes.c_int]),
+        "tbs_plan_autotune": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
         "tbs_profile_enable": (ctypes.c_int, [vp, ctypes.c_int]),
         "tbs_profile_read": (ctypes.c_int, [vp, dp, i64p]),
         "tbs_plan_destroy": (None, [vp]),
@@ -242,6 +243,15 @@ class Plan:
         self._sync_stream()
         _check(library().tbs_green_tabulate(self._h), self._h, "tbs_green_tabulate")
         return self
+
+    def autotune(self):
+        """Pick the fastest block shapes for this plan (bitwise-neutral);
+        returns (rows per row-pass block, columns per convolution block)."""
+        nr, nc = ctypes.c_int(), ctypes.c_int()
+        self._sync_stream()
+        _check(library().tbs_plan_autotune(self._h, ctypes.byref(nr), ctypes.byref(nc)), self._h,
+               "tbs_plan_autotune")
+        return nr.value, nc.value
 
     def import_spectrum(self, full: np.ndarray):
         Mx, My, Mz = self.padded

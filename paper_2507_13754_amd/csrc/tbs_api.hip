@@ -3,7 +3,10 @@
 // sequence, and the per-term pass sequence of the Born series.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -27,12 +30,17 @@ struct tbs_plan {
   bool fp64 = false;
   int batch = 1;
   int cb = 4;
+  int row_nr = 0;           // rows per row-pass block (autotuned; 0 = default)
+  int conv_nc = 0;          // columns per convolution block (autotuned; 0 = default)
   size_t esz = 8;
   int64_t P = 0;
   hipStream_t stream = nullptr;
   int device = 0;
   // device buffers
   void* X = nullptr;        // x-spectral intermediate [B][M_x/cb][rows][cb]
+  void* xcur = nullptr;     // intermediate the passes work on (X, or the adjoint state)
+  void* Xadj = nullptr;     // second intermediate (adjoint state while the forward is recomputed)
+  size_t X_bytes = 0;
   void* Yb = nullptr;       // 3D y-spectral intermediate [B][M_x/cb][M_y][N_z][cb]
   void* kc = nullptr;       // Kahan compensation [B][P] (C64)
   void* ghat = nullptr;     // folded spectrum
@@ -201,7 +209,7 @@ struct ProfScope {
 };
 
 int row_blocks(const tbs_plan* p) {
-  const int NR = tbs::row_rows_per_block((int)p->M[0], p->fp64);
+  const int NR = p->row_nr ? p->row_nr : tbs::row_rows_per_block((int)p->M[0], p->fp64);
   const int64_t rows = p->N[1] * p->N[2];
   return (int)((rows + NR - 1) / NR);
 }
@@ -211,7 +219,7 @@ tbs::RowArgs make_row_args(tbs_plan* p, int in_mode, int acc, int out_spec, bool
                            const void* src, const void* V, void* pacc, void* pstore_slot,
                            const void* pair, void* grad, double* partials) {
   tbs::RowArgs a{};
-  a.X = p->X;
+  a.X = p->xcur;
   a.src = src;
   a.V = V;
   a.p = pacc;
@@ -242,7 +250,14 @@ int run_row(tbs_plan* p, int in_mode, int acc, int out_spec, bool adjoint, const
   const tbs::RowArgs a = make_row_args(p, in_mode, acc, out_spec, adjoint, src, V, pacc,
                                        pstore_slot, pair, grad, partials);
   ProfScope ps(p, in_mode == tbs::ROW_IN_SOURCE ? PK_ROW_FIRST : (out_spec ? PK_ROW_MID : PK_ROW_LAST));
-  TBS_LAUNCH(p, tbs::launch_row_pass(p->fp64, (int)p->M[0], a, row_blocks(p), p->stream));
+  TBS_LAUNCH(p, tbs::launch_row_pass(p->fp64, (int)p->M[0], a, row_blocks(p), p->row_nr, p->stream));
+  return TBS_OK;
+}
+
+// Row pass with prepared arguments.
+int run_row_args(tbs_plan* p, const tbs::RowArgs& a, int kind) {
+  ProfScope ps(p, kind);
+  TBS_LAUNCH(p, tbs::launch_row_pass(p->fp64, (int)p->M[0], a, row_blocks(p), p->row_nr, p->stream));
   return TBS_OK;
 }
 
@@ -251,8 +266,8 @@ tbs::ColArgs make_conv2d_args(tbs_plan* p, bool adjoint, int* nc) {
   const int64_t cb = p->cb;
   const int64_t nkb = p->M[0] / cb;
   tbs::ColArgs a{};
-  a.in = p->X;
-  a.out = p->X;
+  a.in = p->xcur;
+  a.out = p->xcur;
   a.tw = p->tw[1];
   a.ghat = p->ghat;
   a.op = tbs::COL_CONV;
@@ -263,7 +278,7 @@ tbs::ColArgs make_conv2d_args(tbs_plan* p, bool adjoint, int* nc) {
   a.in_rs = a.out_rs = nkb * p->N[1] * cb;
   a.in_s1 = a.out_s1 = p->N[1] * cb;
   a.in_s0 = a.out_s0 = 0;
-  *nc = tbs::conv_cols_per_block((int)p->M[1], p->fp64, (int)cb);
+  *nc = p->conv_nc ? p->conv_nc : tbs::conv_cols_per_block((int)p->M[1], p->fp64, (int)cb);
   a.nrhs = p->batch;
   a.sub = (int)cb / *nc;
   a.n1 = (int)nkb * a.sub;
@@ -276,6 +291,7 @@ tbs::ColArgs make_conv2d_args(tbs_plan* p, bool adjoint, int* nc) {
   a.g_sx = p->M[1] / 2 + 1;
   a.g_sm = 0;
   a.xcd_remap = 1;
+  a.mirror = 1;
   return a;
 }
 
@@ -308,7 +324,7 @@ int run_cols(tbs_plan* p, bool adjoint) {
   // A element (rhs, kxb, y, z, c): ((rhs*nkb + kxb)*ny + y)*nz*cb + z*cb + c
   // B element (rhs, kxb, ky, z, c): ((rhs*nkb + kxb)*my + ky)*nz*cb + z*cb + c
   tbs::ColArgs f = y;
-  f.in = p->X;
+  f.in = p->xcur;
   f.out = p->Yb;
   f.op = tbs::COL_FWD;
   f.n_in = (int)ny;
@@ -351,6 +367,7 @@ int run_cols(tbs_plan* p, bool adjoint) {
   z.g_sx = (p->M[1] / 2 + 1) * (p->M[2] / 2 + 1);
   z.g_sm = p->M[2] / 2 + 1;
   z.xcd_remap = 1;
+  z.mirror = 1;
   {
     ProfScope ps(p, PK_COL_CONV);
     TBS_LAUNCH(p, tbs::launch_col_pass(p->fp64, (int)p->M[2], (int)cb, z, p->stream));
@@ -358,7 +375,7 @@ int run_cols(tbs_plan* p, bool adjoint) {
 
   tbs::ColArgs iv = y;
   iv.in = p->Yb;
-  iv.out = p->X;
+  iv.out = p->xcur;
   iv.op = tbs::COL_INV;
   iv.n_in = (int)my;
   iv.n_out = (int)ny;
@@ -451,7 +468,7 @@ struct tbs_batch {
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   bool fp64 = false;
   struct Group {
-    int M = 0, cb = 4, nc = 0;
+    int M = 0, cb = 4, nc = 0, nr = 0;
     std::vector<int> members;  // plan indices
     int first = 0;             // index of the first member in the descriptor order
     int starts_off = 0;        // offset of this group's starts array
@@ -502,7 +519,7 @@ int batch_enqueue(tbs_batch* b, int L) {
   const int* dst = (const int*)b->d_starts;
   for (int n = 0; n <= L; ++n) {
     for (const auto& g : b->rgroups) {
-      int e = tbs::launch_row_group(b->fp64, g.M, g.cb, drow + (size_t)n * np + g.first,
+      int e = tbs::launch_row_group(b->fp64, g.M, g.cb, g.nr, drow + (size_t)n * np + g.first,
                                     dst + g.starts_off, (int)g.members.size(), g.total, b->stream);
       if (e) return bfail(b, TBS_ERR_HIP, std::string("grouped row pass: ") + hipGetErrorString((hipError_t)e));
     }
@@ -518,6 +535,105 @@ int batch_enqueue(tbs_batch* b, int L) {
     if (e) return bfail(b, TBS_ERR_HIP, std::string("norms: ") + hipGetErrorString((hipError_t)e));
   }
   return TBS_OK;
+}
+
+// Adjoint with recomputation: the forward series is run once keeping
+// checkpoints (u_{cK}, P_{cK+1}) every K = ceil(sqrt(2L)) terms; the adjoint
+// series then walks the segments from last to first, recomputing each
+// segment's partial sums from its checkpoint (in the plan's X) while the
+// adjoint state waits in a second intermediate.  Memory: 2 ceil((L-1)/K) + K + 1
+// fields of [B][P] instead of L.
+int adjoint_recompute(tbs_plan* p, const void* source, const void* V, int L, const void* q,
+                      void* grad, double* residual_out) {
+  const size_t slot = (size_t)p->batch * p->P * p->esz;
+  const int K = std::max(1, (int)std::ceil(std::sqrt(2.0 * L)));
+  const int C = (L - 2) / K + 1;  // checkpoints at terms 0, K, ..., (C-1)K <= L-2
+  const size_t need = slot * (size_t)(2 * C + K + 1);
+  if (p->ckpt_bytes < need) {
+    dev_free(p, p->ckpt, p->ckpt_bytes);
+    p->ckpt_bytes = 0;
+    int rc = dev_alloc(p, &p->ckpt, need);
+    if (rc) return rc;
+    p->ckpt_bytes = need;
+  }
+  if (!p->Xadj) {
+    int rc = dev_alloc(p, &p->Xadj, p->X_bytes);
+    if (rc) return rc;
+  }
+  char* base = (char*)p->ckpt;
+  auto ck_u = [&](int c) { return (void*)(base + (size_t)(2 * c) * slot); };
+  auto ck_p = [&](int c) { return (void*)(base + (size_t)(2 * c + 1) * slot); };
+  auto seg = [&](int j) { return (void*)(base + (size_t)(2 * C + j) * slot); };
+  void* pacc = base + (size_t)(2 * C + K) * slot;
+  const int nblk = row_blocks(p);
+  const size_t per_term = (size_t)2 * p->batch * nblk;
+  int rc = ensure_doubles(p, &p->partials, &p->partials_cap, per_term * (size_t)L);
+  if (!rc) rc = ensure_doubles(p, &p->resid, &p->resid_cap, (size_t)p->batch * L);
+  if (rc) return rc;
+  p->xcur = p->X;
+  // 1. forward series with checkpoints (and the residuals of every term)
+  rc = run_row(p, tbs::ROW_IN_SOURCE, tbs::ACC_NONE, 1, false, source, nullptr, nullptr, nullptr,
+               nullptr, nullptr, nullptr);
+  if (!rc) rc = run_cols(p, false);
+  for (int n = 1; n <= L && !rc; ++n) {
+    tbs::RowArgs a = make_row_args(p, tbs::ROW_IN_SPECTRAL, n == 1 ? tbs::ACC_INIT : tbs::ACC_ADD,
+                                   n < L ? 1 : 0, false, nullptr, V, pacc, nullptr, nullptr, nullptr,
+                                   p->partials + (size_t)(n - 1) * per_term);
+    if ((n - 1) % K == 0 && (n - 1) / K < C) {  // term u_{n-1} and P_n are checkpoint c
+      a.ustore = ck_u((n - 1) / K);
+      a.pstore = ck_p((n - 1) / K);
+    }
+    rc = run_row_args(p, a, n < L ? PK_ROW_MID : PK_ROW_LAST);
+    if (!rc && n < L) rc = run_cols(p, false);
+  }
+  if (!rc) {
+    int e = tbs::launch_finish_norms(p->partials, L, L, p->batch, nblk, p->resid, p->stream);
+    if (e) rc = hip_fail(p, (hipError_t)e, "norms");
+  }
+  if (!rc && residual_out) {
+    rc = check_residuals(p, residual_out, L);
+    if (rc > 0) rc = TBS_OK;
+  }
+  if (rc) return rc;
+  // 2. adjoint start: w_0 = G^H q into the adjoint state
+  p->xcur = p->Xadj;
+  rc = run_row(p, tbs::ROW_IN_SOURCE, tbs::ACC_NONE, 1, true, q, nullptr, nullptr, nullptr, nullptr,
+               nullptr, nullptr);
+  if (!rc) rc = run_cols(p, true);
+  p->xcur = p->X;
+  // 3. segments from last to first
+  for (int c = C - 1; c >= 0 && !rc; --c) {
+    const int lo = c * K + 1;               // P_lo is the checkpoint
+    const int hi = std::min(c * K + K, L - 1);
+    TBS_HIP(p, hipMemcpyAsync(seg(0), ck_p(c), slot, hipMemcpyDeviceToDevice, p->stream));
+    if (hi > lo) {
+      TBS_HIP(p, hipMemcpyAsync(pacc, ck_p(c), slot, hipMemcpyDeviceToDevice, p->stream));
+      if (p->kc) TBS_LAUNCH(p, tbs::launch_zero(p->kc, (int64_t)slot, p->stream));
+      tbs::RowArgs a = make_row_args(p, tbs::ROW_IN_SPATIAL, tbs::ACC_NONE, 1, false, ck_u(c), V,
+                                     nullptr, nullptr, nullptr, nullptr, nullptr);
+      rc = run_row_args(p, a, PK_ROW_FIRST);
+      if (!rc) rc = run_cols(p, false);
+      for (int n = lo + 1; n <= hi && !rc; ++n) {  // accumulates u_{n-1}: P_n
+        tbs::RowArgs b = make_row_args(p, tbs::ROW_IN_SPECTRAL, tbs::ACC_ADD, n < hi ? 1 : 0, false,
+                                       nullptr, V, pacc, seg(n - lo), nullptr, nullptr,
+                                       p->partials);
+        rc = run_row_args(p, b, n < hi ? PK_ROW_MID : PK_ROW_LAST);
+        if (!rc && n < hi) rc = run_cols(p, false);
+      }
+    }
+    // adjoint steps pairing with P_hi .. P_lo
+    p->xcur = p->Xadj;
+    for (int Kp = hi; Kp >= lo && !rc; --Kp) {
+      const int m = L - 1 - Kp;
+      const bool more = m < L - 2;
+      rc = run_row(p, tbs::ROW_IN_SPECTRAL, tbs::ACC_PAIR, more ? 1 : 0, true, nullptr, V, nullptr,
+                   nullptr, seg(Kp - lo), grad, p->partials);
+      if (!rc && more) rc = run_cols(p, true);
+    }
+    p->xcur = p->X;
+  }
+  p->xcur = p->X;
+  return rc;
 }
 
 }  // namespace
@@ -602,6 +718,7 @@ void tbs_plan_destroy(tbs_plan* p) {
   if (!p) return;
   (void)hipStreamSynchronize(p->stream);
   dev_free(p, p->X, 0);
+  dev_free(p, p->Xadj, 0);
   dev_free(p, p->Yb, 0);
   dev_free(p, p->kc, 0);
   dev_free(p, p->ghat, 0);
@@ -663,7 +780,9 @@ int tbs_plan_create(tbs_plan** out, int ndim, const int64_t grid[3], double dx, 
   }
   const size_t B = (size_t)batch;
   const size_t xe = B * p->M[0] * p->N[1] * p->N[2];
-  int rc = dev_alloc(p, &p->X, xe * p->esz);
+  p->X_bytes = xe * p->esz;
+  int rc = dev_alloc(p, &p->X, p->X_bytes);
+  p->xcur = p->X;
   if (!rc && ndim == 3) rc = dev_alloc(p, &p->Yb, B * p->M[0] * p->M[1] * p->N[2] * p->esz);
   if (!rc && !p->fp64) rc = dev_alloc(p, &p->kc, B * p->P * p->esz);
   p->ghat_n = (p->M[0] / 2 + 1) * (p->M[1] / 2 + 1) * (ndim == 3 ? p->M[2] / 2 + 1 : 1);
@@ -858,6 +977,7 @@ int tbs_adjoint(tbs_plan* p, const void* source, const void* V, int L, const voi
     }
     return TBS_OK;
   }
+  if (flags == TBS_ADJ_RECOMPUTE) return adjoint_recompute(p, source, V, L, q, grad, residual_out);
   // Forward pass keeping the partial sums P_1..P_{L-1} (the final p is not needed).
   const size_t need = slot * (size_t)(L - 1);
   if (p->pstore_bytes < need) {
@@ -920,6 +1040,110 @@ int tbs_speed_gradient(tbs_plan* p, const void* g, const void* dVdc, double* gra
   return TBS_OK;
 }
 
+int tbs_plan_autotune(tbs_plan* p, int* row_nr_out, int* conv_nc_out) {
+  if (!p) return TBS_ERR_INVALID;
+  if (!p->green_ready) return fail(p, TBS_ERR_STATE, "tabulate the spectrum before tuning");
+  if (p->ndim == 2) {
+    static std::mutex mu;
+    static std::map<std::vector<int64_t>, std::pair<int, int>> cache;
+    const std::vector<int64_t> key = {p->device, p->N[0], p->N[1], p->M[0], p->M[1], p->batch,
+                                      p->fp64 ? 1 : 0};
+    bool hit = false;
+    {
+      std::lock_guard<std::mutex> g(mu);
+      auto it = cache.find(key);
+      if (it != cache.end()) {
+        p->row_nr = it->second.first;
+        p->conv_nc = it->second.second;
+        hit = true;
+      }
+    }
+    if (!hit) {
+      const size_t slot = (size_t)p->batch * p->P * p->esz;
+      void* pacc = nullptr;
+      void* vz = nullptr;
+      int rc = dev_alloc(p, &pacc, slot);
+      if (!rc) rc = dev_alloc(p, &vz, (size_t)p->P * p->esz);
+      const size_t per_term = (size_t)2 * p->batch * (size_t)p->N[1];  // >= 2 * batch * row blocks
+      if (!rc) rc = ensure_doubles(p, &p->partials, &p->partials_cap, per_term);
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (!rc && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+        rc = hip_fail(p, hipErrorOutOfMemory, "events");
+      if (!rc) {
+        (void)tbs::launch_zero(pacc, (int64_t)slot, p->stream);
+        (void)tbs::launch_zero(vz, (int64_t)(p->P * p->esz), p->stream);
+        (void)tbs::launch_zero(p->X, (int64_t)p->X_bytes, p->stream);
+        if (p->kc) (void)tbs::launch_zero(p->kc, (int64_t)slot, p->stream);
+      }
+      auto timeit = [&](auto&& fn) -> double {
+        for (int w = 0; w < 2; ++w) fn();
+        (void)hipEventRecord(e0, p->stream);
+        for (int r = 0; r < 5; ++r) fn();
+        (void)hipEventRecord(e1, p->stream);
+        (void)hipEventSynchronize(e1);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        return ms / 5.0;
+      };
+      int cand[8];
+      if (!rc) {
+        const int nrn = tbs::row_nr_candidates((int)p->M[0], p->fp64, cand);
+        double best = 1e30;
+        int pick = cand[0];
+        for (int i = 0; i < nrn; ++i) {
+          p->row_nr = cand[i];
+          const tbs::RowArgs a = make_row_args(p, tbs::ROW_IN_SPECTRAL, tbs::ACC_ADD, 1, false, nullptr,
+                                               vz, pacc, nullptr, nullptr, nullptr, p->partials);
+          const double t = timeit([&] {
+            (void)tbs::launch_row_pass(p->fp64, (int)p->M[0], a, row_blocks(p), p->row_nr, p->stream);
+          });
+          if (t < best) {
+            best = t;
+            pick = cand[i];
+          }
+        }
+        p->row_nr = pick;
+        const int ncn = tbs::conv_nc_candidates((int)p->M[1], p->fp64, p->cb, cand);
+        best = 1e30;
+        pick = cand[0];
+        for (int i = 0; i < ncn; ++i) {
+          p->conv_nc = cand[i];
+          int nc = 0;
+          const tbs::ColArgs c = make_conv2d_args(p, false, &nc);
+          const double t = timeit([&] {
+            (void)tbs::launch_col_pass(p->fp64, (int)p->M[1], nc, c, p->stream);
+          });
+          if (t < best) {
+            best = t;
+            pick = cand[i];
+          }
+        }
+        p->conv_nc = pick;
+        hipError_t he = hipStreamSynchronize(p->stream);
+        if (he != hipSuccess) rc = hip_fail(p, he, "autotune");
+      }
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+      dev_free(p, pacc, slot);
+      dev_free(p, vz, (size_t)p->P * p->esz);
+      if (rc) {
+        p->row_nr = 0;
+        p->conv_nc = 0;
+        return rc;
+      }
+      std::lock_guard<std::mutex> g(mu);
+      cache[key] = {p->row_nr, p->conv_nc};
+    }
+  }
+  if (row_nr_out) *row_nr_out = p->row_nr ? p->row_nr : tbs::row_rows_per_block((int)p->M[0], p->fp64);
+  if (conv_nc_out) {
+    int nc = 0;
+    if (p->ndim == 2) (void)make_conv2d_args(p, false, &nc);
+    *conv_nc_out = nc;
+  }
+  return TBS_OK;
+}
+
 int tbs_profile_enable(tbs_plan* p, int enable) {
   if (!p) return TBS_ERR_INVALID;
   TBS_HIP(p, hipStreamSynchronize(p->stream));
@@ -976,21 +1200,22 @@ int tbs_batch_create(tbs_batch** out, tbs_plan* const* plans, int nplans) {
   // group by padded length (rows: M_x; columns: M_y and the column shape)
   b->rpos.assign(nplans, 0);
   b->cpos.assign(nplans, 0);
-  auto find_or_add = [](std::vector<tbs_batch::Group>& gs, int M, int cb, int nc) -> tbs_batch::Group& {
+  auto find_or_add = [](std::vector<tbs_batch::Group>& gs, int M, int cb, int nc, int nr) -> tbs_batch::Group& {
     for (auto& g : gs)
-      if (g.M == M && g.cb == cb && g.nc == nc) return g;
+      if (g.M == M && g.cb == cb && g.nc == nc && g.nr == nr) return g;
     gs.push_back(tbs_batch::Group());
     gs.back().M = M;
     gs.back().cb = cb;
     gs.back().nc = nc;
+    gs.back().nr = nr;
     return gs.back();
   };
   for (int i = 0; i < nplans; ++i) {
     tbs_plan* p = b->plans[i];
-    find_or_add(b->rgroups, (int)p->M[0], p->cb, 0).members.push_back(i);
+    find_or_add(b->rgroups, (int)p->M[0], p->cb, 0, p->row_nr).members.push_back(i);
     int nc = 0;
     (void)make_conv2d_args(p, false, &nc);
-    find_or_add(b->cgroups, (int)p->M[1], p->cb, nc).members.push_back(i);
+    find_or_add(b->cgroups, (int)p->M[1], p->cb, nc, 0).members.push_back(i);
   }
   std::vector<int> starts;
   int pos = 0;

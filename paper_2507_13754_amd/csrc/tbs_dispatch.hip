@@ -45,11 +45,37 @@ int conv_cols_per_block(int M, bool fp64, int cb) {
 
 int col_max_cols(int M, bool fp64) {
   const int esz = fp64 ? 16 : 8;
+  (void)esz;
   return col_fits(M, 4, esz) ? 4 : (col_fits(M, 2, esz) ? 2 : 1);
 }
 
-int launch_row_pass(bool fp64, int M, const RowArgs& a, int nblk_rows, hipStream_t s) {
+int row_nr_candidates(int M, bool fp64, int* out) {
+  const int esz = fp64 ? 16 : 8;
+  int n = 0;
+  out[n++] = rows_per_block(M, fp64);
+  if (M >= 2048) {
+    for (int nr : {2, 4})
+      if (nr != out[0] && row_fits(M, nr, esz)) out[n++] = nr;
+  }
+  return n;
+}
+
+int conv_nc_candidates(int M, bool fp64, int cb, int* out) {
+  const int esz = fp64 ? 16 : 8;
+  int n = 0;
+  out[n++] = conv_cols_per_block(M, fp64, cb);
+  for (int nc : {1, 2, 4}) {
+    if (nc == out[0] || nc > cb || cb % nc) continue;
+    if (nc == 1 && M < 2048) continue;
+    if (!col_fits(M, nc, esz)) continue;
+    out[n++] = nc;
+  }
+  return n;
+}
+
+int launch_row_pass(bool fp64, int M, const RowArgs& a, int nblk_rows, int nr, hipStream_t s) {
   PassReq q;
+  q.nr = nr;
   q.kind = PASS_ROW;
   q.fp64 = fp64;
   q.M = M;
@@ -80,9 +106,10 @@ int launch_row_fft_full(int M, void* data, const void* tw, int nrows, int invers
   return family(q, s);
 }
 
-int launch_row_group(bool fp64, int M, int cb, const RowArgs* descs, const int* starts, int ngroups,
-                     int total_blocks, hipStream_t s) {
+int launch_row_group(bool fp64, int M, int cb, int nr, const RowArgs* descs, const int* starts,
+                     int ngroups, int total_blocks, hipStream_t s) {
   PassReq q;
+  q.nr = nr;
   q.kind = PASS_ROW_GROUP;
   q.fp64 = fp64;
   q.M = M;

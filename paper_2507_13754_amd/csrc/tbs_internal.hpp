@@ -10,7 +10,9 @@ namespace tbs {
 // intermediate X: [rhs][M/CB][nrows][CB], CB = kBlock columns per block, rows
 // ordered rho = y*nz + z (3D) / rho = y (2D).  Spatial arrays (source, p, c,
 // V, pairing, gradient) are [rhs][z][y][x] / [z][y][x].
-enum RowIn { ROW_IN_SOURCE = 0, ROW_IN_SPECTRAL = 1 };
+// ROW_IN_SOURCE: w = src; ROW_IN_SPECTRAL: u = crop(IFFT(X)); ROW_IN_SPATIAL:
+// w = V src (restart of a series from a stored spatial term).
+enum RowIn { ROW_IN_SOURCE = 0, ROW_IN_SPECTRAL = 1, ROW_IN_SPATIAL = 2 };
 enum RowAcc { ACC_NONE = 0, ACC_INIT = 1, ACC_ADD = 2, ACC_PAIR = 3 };
 
 // Spectral columns per contiguous block (cb) is 4, or 2 for FP64 plans with
@@ -22,6 +24,7 @@ struct RowArgs {
   const void* V;        // potential [P] (OUT) ; nullptr = multiply by 0
   void* p;              // accumulator [rhs][P]
   void* pstore;         // optional copy of the updated accumulator [rhs][P]
+  void* ustore;         // optional copy of the term u itself [rhs][P]
   void* c;              // Kahan compensation [rhs][P] (FP32 only)
   const void* pair;     // ACC_PAIR: partial sums P_{L-1-m} [rhs][P]
   void* grad;           // ACC_PAIR: g_V accumulator [rhs][P]
@@ -48,6 +51,7 @@ struct ColArgs {
   int nrhs, n1, n0;
   int cb;               // spectral block width of the layout
   int sub;              // blocks per layout block (block holds cb/sub columns); 1 otherwise
+  int mirror;           // launch mirror-image columns (shared spectrum lines) back to back
   int zcols, zlim;      // column validity: i0*zcols + col/cb < zlim
   int mx, mm;           // fold sizes of kx (= i1*cb + col%cb) and kmid (= i0)
   int64_t g_sx, g_sm;   // table strides for fold(kx), fold(kmid)
@@ -68,6 +72,7 @@ struct PassReq {
   bool fp64 = false;
   int M = 0;
   int nc = 0;                       // columns per block (column passes)
+  int nr = 0;                       // rows per row-pass block (0: default)
   int cb = 4;                       // layout block width (grouped row passes)
   const RowArgs* row = nullptr;     // PASS_ROW
   int nblk_rows = 0;
@@ -93,12 +98,15 @@ int spectral_block(int My, bool fp64);
 int col_max_cols(int M, bool fp64);  // widest column block that fits LDS
 int conv_cols_per_block(int M, bool fp64, int cb);  // columns per convolution block
 // Launchers (return hipError_t as int).
-int launch_row_pass(bool fp64, int M, const RowArgs& a, int nblk_rows, hipStream_t s);
+int launch_row_pass(bool fp64, int M, const RowArgs& a, int nblk_rows, int nr, hipStream_t s);
+// Block-shape candidates the autotuner may pick for a line length.
+int row_nr_candidates(int M, bool fp64, int* out);      // returns count
+int conv_nc_candidates(int M, bool fp64, int cb, int* out);
 int launch_col_pass(bool fp64, int M, int NC, const ColArgs& a, hipStream_t s);
 int launch_row_fft_full(int M, void* data, const void* tw, int nrows, int inverse, hipStream_t s);
 // Grouped launches (descs/starts are device arrays of ngroups entries).
-int launch_row_group(bool fp64, int M, int cb, const RowArgs* descs, const int* starts, int ngroups,
-                     int total_blocks, hipStream_t s);
+int launch_row_group(bool fp64, int M, int cb, int nr, const RowArgs* descs, const int* starts,
+                     int ngroups, int total_blocks, hipStream_t s);
 int launch_col_group(bool fp64, int M, int nc, const ColArgs* descs, const int* starts, int ngroups,
                      int total_blocks, hipStream_t s);
 

@@ -77,6 +77,15 @@ __device__ __forceinline__ double norm2(cx<T> a) {
 
 __device__ __forceinline__ int fold(int k, int m) { return k <= (m >> 1) ? k : m - k; }
 
+// Launch order pairing the mirror images k, n-k (n even): 0, 1, n-1, 2, n-2,
+// ..., n/2-1, n/2+1, n/2.  A bijection of [0, n); identity for odd n.
+__device__ __forceinline__ int mirror_pair(int l, int n) {
+  if ((n & 1) || l == 0) return l;
+  if (l == n - 1) return n >> 1;
+  const int k = (l + 1) >> 1;
+  return (l & 1) ? k : n - k;
+}
+
 // ---------------------------------------------------------------- row pass --
 
 template <typename T, int M, int E, int NR, int CB, bool SPLIT>
@@ -131,6 +140,7 @@ __device__ __forceinline__ void row_pass_body(const RowArgs& a, const int lb) {
       if (j < E / 2 && valid && x < a.nx) {
         const int64_t i = sp_base + x;
         const cx<T> u = v[j];
+        if (a.ustore) ((cx<T>*)a.ustore)[i] = u;
         if (a.acc == ACC_INIT) {
           p[i] = u;
           if (a.pstore) ((cx<T>*)a.pstore)[i] = u;
@@ -168,10 +178,19 @@ __device__ __forceinline__ void row_pass_body(const RowArgs& a, const int lb) {
     }
   } else {
     const cx<T>* src = (const cx<T>*)a.src;
+    const cx<T>* Vp = (const cx<T>*)a.V;
 #pragma unroll
     for (int j = 0; j < E; ++j) {
       const int x = t + j * TPT;
-      v[j] = (j < E / 2 && valid && x < a.nx) ? src[sp_base + x] : cx<T>{T(0), T(0)};
+      cx<T> w = {T(0), T(0)};
+      if (j < E / 2 && valid && x < a.nx) {
+        w = src[sp_base + x];
+        if (a.in_mode == ROW_IN_SPATIAL) {
+          const cx<T> vv = Vp[srow + x];
+          w = a.conj_v ? cmulc(w, vv) : cmul(w, vv);
+        }
+      }
+      v[j] = w;
     }
   }
 
@@ -224,8 +243,13 @@ __device__ __forceinline__ void col_pass_body(const ColArgs& a, const int lb) {
   const int tt = tid / NC;
   const int rhs = lb % a.nrhs;
   const int rest = lb / a.nrhs;
-  const int i0 = rest % a.n0;
-  const int i1 = rest / a.n0;
+  int i0 = rest % a.n0;
+  int i1 = rest / a.n0;
+  if (a.mirror) {
+    // neighbours in launch order read the same folded spectrum lines
+    i0 = mirror_pair(i0, a.n0);
+    i1 = mirror_pair(i1 / a.sub, a.n1 / a.sub) * a.sub + i1 % a.sub;
+  }
   const bool cvalid = (i0 * a.zcols + col / a.cb) < a.zlim;
   LdsT* shc = sh + col * LD;
   const cx<T>* tw = (const cx<T>*)a.tw;
@@ -347,23 +371,32 @@ constexpr int elems_per_thread(int M, bool fp64) {
   if (!fp64 && ((r == 3 && M >= 384) || (r == 5 && M >= 640))) return 8 * r;
   return 4 * r;
 }
-constexpr bool split_lds(int M) { return M >= TBS_SPLIT_MIN; }
+// Exchanges split into real and imaginary rounds (half the LDS per line) for
+// lines whose many values per thread would otherwise leave few lines per CU.
+constexpr bool split_lds(int M, bool fp64) {
+  return M >= TBS_SPLIT_MIN || (odd_part(M) > 1 && elems_per_thread(M, fp64) >= 24);
+}
 constexpr int rows_per_block(int M, bool fp64) {
-  return fp64 ? (M >= 4096 ? TBS_NR_F64 : (M >= 2048 && !split_lds(M) ? 2 : 4))
+  return fp64 ? (M >= 4096 ? TBS_NR_F64 : (M >= 2048 && !split_lds(M, true) ? 2 : 4))
               : (M >= 2048 ? TBS_NR_F32 : 4);
 }
 constexpr bool col_fits(int M, int NC, int esz) {
-  return (long)NC * lds_len(M) * (split_lds(M) ? esz / 2 : esz) <= 160L * 1024;
+  return (long)NC * lds_len(M) * (split_lds(M, esz == 16) ? esz / 2 : esz) <= 160L * 1024;
 }
 
 // ------------------------------------------------------ launch templates --
 
-template <typename T, int M>
-int row_launch(const RowArgs& a, int nblk_rows, hipStream_t s) {
+constexpr bool row_fits(int M, int NR, int esz) {
+  return (long)NR * lds_len(M) * (split_lds(M, esz == 16) ? esz / 2 : esz) <= 160L * 1024;
+}
+
+// Row-pass block shapes: the default NR, or (lines of 2048+) 2 or 4 rows when
+// they fit LDS; nr = 0 selects the default.
+template <typename T, int M, int NR>
+int row_launch_nr(const RowArgs& a, int nblk_rows, hipStream_t s) {
   constexpr bool F64 = sizeof(T) == 8;
   constexpr int E = elems_per_thread(M, F64);
-  constexpr int NR = rows_per_block(M, F64);
-  constexpr bool SP = split_lds(M);
+  constexpr bool SP = split_lds(M, F64);
   const int grid = nblk_rows * a.nrhs;
   if (a.cb == 4) {
     hipLaunchKernelGGL((k_row_pass<T, M, E, NR, 4, SP>), dim3(grid), dim3(NR * (M / E)), 0, s, a);
@@ -376,12 +409,26 @@ int row_launch(const RowArgs& a, int nblk_rows, hipStream_t s) {
 }
 
 template <typename T, int M>
-int row_group_launch(const RowArgs* descs, const int* starts, int ngroups, int total, int cb,
-                     hipStream_t s) {
+int row_launch(const RowArgs& a, int nblk_rows, int nr, hipStream_t s) {
+  constexpr bool F64 = sizeof(T) == 8;
+  constexpr int NRD = rows_per_block(M, F64);
+  constexpr int esz = (int)sizeof(cx<T>);
+  if (nr == 0 || nr == NRD) return row_launch_nr<T, M, NRD>(a, nblk_rows, s);
+  if constexpr (M >= 2048 && NRD != 2 && row_fits(M, 2, esz)) {
+    if (nr == 2) return row_launch_nr<T, M, 2>(a, nblk_rows, s);
+  }
+  if constexpr (M >= 2048 && NRD != 4 && row_fits(M, 4, esz)) {
+    if (nr == 4) return row_launch_nr<T, M, 4>(a, nblk_rows, s);
+  }
+  return (int)hipErrorInvalidValue;
+}
+
+template <typename T, int M, int NR>
+int row_group_launch_nr(const RowArgs* descs, const int* starts, int ngroups, int total, int cb,
+                        hipStream_t s) {
   constexpr bool F64 = sizeof(T) == 8;
   constexpr int E = elems_per_thread(M, F64);
-  constexpr int NR = rows_per_block(M, F64);
-  constexpr bool SP = split_lds(M);
+  constexpr bool SP = split_lds(M, F64);
   if (cb == 4) {
     hipLaunchKernelGGL((k_row_pass_group<T, M, E, NR, 4, SP>), dim3(total), dim3(NR * (M / E)), 0, s,
                        descs, starts, ngroups);
@@ -394,10 +441,26 @@ int row_group_launch(const RowArgs* descs, const int* starts, int ngroups, int t
   return (int)hipGetLastError();
 }
 
+template <typename T, int M>
+int row_group_launch(const RowArgs* descs, const int* starts, int ngroups, int total, int cb, int nr,
+                     hipStream_t s) {
+  constexpr bool F64 = sizeof(T) == 8;
+  constexpr int NRD = rows_per_block(M, F64);
+  constexpr int esz = (int)sizeof(cx<T>);
+  if (nr == 0 || nr == NRD) return row_group_launch_nr<T, M, NRD>(descs, starts, ngroups, total, cb, s);
+  if constexpr (M >= 2048 && NRD != 2 && row_fits(M, 2, esz)) {
+    if (nr == 2) return row_group_launch_nr<T, M, 2>(descs, starts, ngroups, total, cb, s);
+  }
+  if constexpr (M >= 2048 && NRD != 4 && row_fits(M, 4, esz)) {
+    if (nr == 4) return row_group_launch_nr<T, M, 4>(descs, starts, ngroups, total, cb, s);
+  }
+  return (int)hipErrorInvalidValue;
+}
+
 template <typename T, int M, int NC>
 int col_launch(const ColArgs& a, hipStream_t s) {
   constexpr int E = elems_per_thread(M, sizeof(T) == 8);
-  constexpr bool SP = split_lds(M);
+  constexpr bool SP = split_lds(M, sizeof(T) == 8);
   const int grid = a.nrhs * a.n1 * a.n0;
   const dim3 blk(NC * (M / E));
   switch (a.op) {
@@ -443,7 +506,7 @@ template <typename T, int M>
 int col_group_launch(int NC, const ColArgs* descs, const int* starts, int ngroups, int total,
                      hipStream_t s) {
   constexpr int E = elems_per_thread(M, sizeof(T) == 8);
-  constexpr bool SP = split_lds(M);
+  constexpr bool SP = split_lds(M, sizeof(T) == 8);
   constexpr int esz = (int)sizeof(cx<T>);
   if constexpr (col_fits(M, 4, esz)) {
     if (NC == 4) {
@@ -459,6 +522,13 @@ int col_group_launch(int NC, const ColArgs* descs, const int* starts, int ngroup
       return (int)hipGetLastError();
     }
   }
+  if constexpr (M >= 2048) {
+    if (NC == 1) {
+      hipLaunchKernelGGL((k_col_pass_group<T, M, E, 1, COL_CONV, SP>), dim3(total), dim3(M / E), 0, s,
+                         descs, starts, ngroups);
+      return (int)hipGetLastError();
+    }
+  }
   return (int)hipErrorInvalidValue;
 }
 
@@ -466,7 +536,7 @@ template <int M>
 int rowfull_launch(void* data, const void* tw, int nrows, int inverse, hipStream_t s) {
   constexpr int E = elems_per_thread(M, true);
   constexpr int NR = rows_per_block(M, true);
-  hipLaunchKernelGGL((k_row_fft_full<double, M, E, NR, split_lds(M)>), dim3((nrows + NR - 1) / NR),
+  hipLaunchKernelGGL((k_row_fft_full<double, M, E, NR, split_lds(M, true)>), dim3((nrows + NR - 1) / NR),
                      dim3(NR * (M / E)), 0, s, (cx<double>*)data, (const cx<double>*)tw, nrows,
                      inverse);
   return (int)hipGetLastError();
@@ -486,16 +556,16 @@ int rowfull_launch(void* data, const void* tw, int nrows, int inverse, hipStream
   case m:                                                                                         \
     switch (q.kind) {                                                                             \
       case PASS_ROW:                                                                              \
-        return q.fp64 ? row_launch<double, m>(*q.row, q.nblk_rows, s)                             \
-                      : row_launch<float, m>(*q.row, q.nblk_rows, s);                             \
+        return q.fp64 ? row_launch<double, m>(*q.row, q.nblk_rows, q.nr, s)                       \
+                      : row_launch<float, m>(*q.row, q.nblk_rows, q.nr, s);                       \
       case PASS_COL:                                                                              \
         return q.fp64 ? col_launch_nc<double, m>(q.nc, *q.col, s)                                 \
                       : col_launch_nc<float, m>(q.nc, *q.col, s);                                 \
       case PASS_ROW_FULL:                                                                         \
         return rowfull_launch<m>(q.data, q.tw, q.nrows, q.inverse, s);                            \
       case PASS_ROW_GROUP:                                                                        \
-        return q.fp64 ? row_group_launch<double, m>(q.row_descs, q.starts, q.ngroups, q.total, q.cb, s) \
-                      : row_group_launch<float, m>(q.row_descs, q.starts, q.ngroups, q.total, q.cb, s); \
+        return q.fp64 ? row_group_launch<double, m>(q.row_descs, q.starts, q.ngroups, q.total, q.cb, q.nr, s) \
+                      : row_group_launch<float, m>(q.row_descs, q.starts, q.ngroups, q.total, q.cb, q.nr, s); \
       case PASS_COL_GROUP:                                                                        \
         return q.fp64 ? col_group_launch<double, m>(q.nc, q.col_descs, q.starts, q.ngroups, q.total, s) \
                       : col_group_launch<float, m>(q.nc, q.col_descs, q.starts, q.ngroups, q.total, s); \

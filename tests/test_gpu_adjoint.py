@@ -33,9 +33,13 @@ def to_dev(a, dev, dt):
     return torch.from_numpy(np.ascontiguousarray(a)).to(dev, tdt(dt))
 
 
+@pytest.mark.parametrize("flags", [0, 1], ids=["store", "recompute"])
 @pytest.mark.parametrize("dt", ["c128", "c64"])
-@pytest.mark.parametrize("shape,L", [((21, 34), 6), ((40, 40), 1), ((40, 40), 2), ((6, 7, 9), 4)])
-def test_adjoint_series_matches_oracle(dev, dt, shape, L):
+@pytest.mark.parametrize("shape,L", [((21, 34), 6), ((40, 40), 1), ((40, 40), 2), ((6, 7, 9), 4),
+                                     ((16, 20), 25), ((18, 12), 13)])
+def test_adjoint_series_matches_oracle(dev, dt, shape, L, flags):
+    """Both adjoint modes: all partial sums stored, or sqrt(2L)-spaced
+    checkpoints with segment recomputation (L = 13, 25: several segments)."""
     import paper_2507_13754_amd as tbs
     dx = 1.0
     k0 = 2 * np.pi / 6 * (1 + 0.02j)
@@ -45,7 +49,7 @@ def test_adjoint_series_matches_oracle(dev, dt, shape, L):
     G = oracle.GreenOperator(k0, dx, shape)
     ref = np.stack([oracle.adjoint_series_gradient(G, s[b], V, L, q[b]) for b in range(2)])
     plan = tbs.Plan(shape, dx, k0, dtype=tdt(dt), batch=2).tabulate()
-    g = plan.adjoint(to_dev(s, dev, dt), to_dev(V, dev, dt), L, to_dev(q, dev, dt))
+    g = plan.adjoint(to_dev(s, dev, dt), to_dev(V, dev, dt), L, to_dev(q, dev, dt), flags=flags)
     g = g.cpu().numpy().astype(np.complex128)
     if L == 1:
         assert np.all(g == 0)

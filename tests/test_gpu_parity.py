@@ -217,3 +217,24 @@ def test_diverging_series_warns(dev):
         warnings.simplefilter("always")
         gpu_solve(dev, (24, 24), dx, k0, s, V, 40, "c128")
     assert any(issubclass(x.category, tbs.TBSWarning) and "DIVERGING" in str(x.message) for x in w)
+
+
+@pytest.mark.parametrize("shape", [(2048, 300), (700, 1000)])
+def test_autotuned_plan_is_bitwise_identical(dev, shape):
+    """The autotuner only changes block shapes: the field is bitwise equal."""
+    import paper_2507_13754_amd as tbs
+    dx, k0, V, s = small_case(shape, seed=37)
+    s = s[:1]
+    L = 4
+    base = tbs.Plan(shape, dx, k0, dtype=torch.complex64).tabulate()
+    tuned = tbs.Plan(shape, dx, k0, dtype=torch.complex64).tabulate()
+    nr, nc = tuned.autotune()
+    assert nr in (2, 4) and nc in (1, 2, 4)
+    sd = torch.from_numpy(s).to(dev, torch.complex64)
+    Vd = torch.from_numpy(V).to(dev, torch.complex64)
+    p0, r0 = base.solve(sd, Vd, L, residual=True)
+    p1, r1 = tuned.solve(sd, Vd, L, residual=True)
+    assert torch.equal(p0, p1)
+    assert np.allclose(r0, r1, rtol=1e-13, atol=0)
+    base.close()
+    tuned.close()
