@@ -330,6 +330,102 @@ def run_adjoint2d(dev, steps: int, warmup: int):
             "value": gpt / (ms * 1e-3), "unit": "grid-point·terms/s (3 series per (f, s))"}
 
 
+# ------------------------------------------------------------------------------
+# rocprofv3 summaries (text under profiles/): parse the CSV output of a
+# --kernel-trace --stats run, or of two --pmc runs (FETCH_SIZE, WRITE_SIZE) of
+# this same script with --calib-copy, and write the per-kernel figures.
+
+KIND_KERNELS = {  # pass kind -> (kernel template name, OP template argument or None)
+    "row_mid": ("k_row_pass<", None),
+    "col_conv": ("k_col_pass<", 0),
+}
+
+
+def _kernel_matches(name: str, kind: str) -> bool:
+    stem, op = KIND_KERNELS[kind]
+    if stem not in name:
+        return False
+    if op is None:
+        return True
+    args = name.split(stem, 1)[1].split(">", 1)[0].split(",")
+    return len(args) >= 5 and args[4].strip() == str(op)
+
+
+def _csv(path):
+    import csv
+    with open(path, newline="") as fh:
+        return list(csv.DictReader(fh))
+
+
+def summarize_trace(src: str, out: str, command: str, title: str):
+    """Per-kernel durations from <src>/run_kernel_trace.csv into a markdown table."""
+    rows = _csv(os.path.join(src, "run_kernel_trace.csv"))
+    agg = {}
+    for r in rows:
+        d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        a = agg.setdefault(r["Kernel_Name"], dict(n=0, tot=0.0, mn=1e30, mx=0.0, lds=r.get("LDS_Block_Size", ""),
+                                                  grid=r.get("Grid_Size_X", ""), block=r.get("Workgroup_Size_X", ""),
+                                                  vgpr=r.get("VGPR_Count", ""), scr=r.get("Scratch_Size", "")))
+        a["n"] += 1
+        a["tot"] += d
+        a["mn"] = min(a["mn"], d)
+        a["mx"] = max(a["mx"], d)
+    lines = [f"# rocprofv3 kernel trace: {title}", "", "Command (repository root as working directory):", "",
+             "    " + command, "",
+             "Per-kernel durations (us) from the kernel trace of that run.", "",
+             "| kernel | calls | total us | avg us | min us | max us | LDS B | VGPR | scratch | grid | block |",
+             "|---|---|---|---|---|---|---|---|---|---|---|"]
+    for k, a in sorted(agg.items(), key=lambda kv: -kv[1]["tot"]):
+        lines.append(f"| `{k}` | {a['n']} | {a['tot']:.1f} | {a['tot'] / a['n']:.2f} | {a['mn']:.2f} | "
+                     f"{a['mx']:.2f} | {a['lds']} | {a['vgpr']} | {a['scr']} | {a['grid']} | {a['block']} |")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    log(f"[bench] wrote {out}")
+
+
+def summarize_counters(src: str, workload: str, command: str):
+    """FETCH_SIZE / WRITE_SIZE per dispatch (KiB) from <src>/fetch and
+    <src>/write, scaled by what the same counters read for the 256 MiB
+    calibration copy, into profiles/counters_<kind>_<workload>.json (+ .md)."""
+    import statistics
+    vals = {}
+    for kind, ctr in (("fetch", "FETCH_SIZE"), ("write", "WRITE_SIZE")):
+        for r in _csv(os.path.join(src, kind, "run_counter_collection.csv")):
+            if r["Counter_Name"] == ctr:
+                vals.setdefault(kind, []).append((r["Kernel_Name"], int(r["Grid_Size"]), float(r["Counter_Value"])))
+    calib = 256 * 1024  # KiB read and written by the calibration copy
+    factor = {}
+    for kind in ("fetch", "write"):
+        copies = [v for n, g, v in vals[kind] if "copyBuffer" in n]
+        big = max(copies)
+        sel = [v for v in copies if v > 0.4 * big]
+        factor[kind] = calib / statistics.median(sel)
+    out = {}
+    md = [f"# HBM traffic counters: {workload}", "", "Commands (repository root as working directory):", "",
+          "    " + command, "",
+          "FETCH_SIZE and WRITE_SIZE in KiB per dispatch (median over dispatches), scaled by the",
+          f"calibration copy of 256 MiB: read factor {factor['fetch']:.3f}, write factor {factor['write']:.3f}.", "",
+          "| pass kind | dispatches | FETCH KiB | WRITE KiB | scaled bytes / launch |", "|---|---|---|---|---|"]
+    for kind in KIND_KERNELS:
+        f = [v for n, g, v in vals["fetch"] if _kernel_matches(n, kind)]
+        w = [v for n, g, v in vals["write"] if _kernel_matches(n, kind)]
+        if not f or not w:
+            continue
+        fk, wk = statistics.median(f), statistics.median(w)
+        traffic = 1024.0 * (fk * factor["fetch"] + wk * factor["write"])
+        out[kind] = traffic
+        md.append(f"| {kind} | {len(f)} | {fk:.1f} | {wk:.1f} | {traffic:.4g} |")
+        with open(os.path.join(ROOT, "profiles", f"counters_{kind}_{workload}.json"), "w") as fh:
+            json.dump({"kind": kind, "workload": workload, "sources_sha256_16": kernel_sources_hash(),
+                       "fetch_kib_median": fk, "write_kib_median": wk, "read_factor": factor["fetch"],
+                       "write_factor": factor["write"], "traffic_bytes_per_launch": traffic,
+                       "command": command}, fh, indent=1)
+    md += ["", f"Kernel sources hash: {kernel_sources_hash()} (bench.py reports the traffic only while it matches)."]
+    with open(os.path.join(ROOT, "profiles", f"counters_{workload}.md"), "w") as fh:
+        fh.write("\n".join(md) + "\n")
+    log(f"[bench] counters: {out}")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -344,7 +440,20 @@ def main():
                     help="also run a plain 256 MiB device copy (counter calibration)")
     ap.add_argument("--extra", default="broadband,harmonic3d,adjoint2d",
                     help="comma-separated side workloads reported in the same line ('' for none)")
+    ap.add_argument("--summarize-trace", metavar="DIR",
+                    help="write a kernel-trace summary of a rocprofv3 CSV run (no GPU work)")
+    ap.add_argument("--summarize-counters", metavar="DIR",
+                    help="write traffic summaries of FETCH_SIZE/WRITE_SIZE runs (no GPU work)")
+    ap.add_argument("--summary-out", default=None)
+    ap.add_argument("--summary-command", default="")
+    ap.add_argument("--summary-title", default="")
     args = ap.parse_args()
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace, args.summary_out, args.summary_command, args.summary_title)
+        return
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters, args.workload, args.summary_command)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         log("bench.py measures one GPU: this build runs the hot path on a single MI355X "
             "(frequencies/sources would shard across GPUs with no communication); use --gpus 1")

@@ -170,6 +170,21 @@ int tbs_solve(tbs_plan *plan, const void *source, const void *potential, int nte
 int tbs_harmonic_source(tbs_plan *plan, const void *p1_dev, const double *c_dev, double omega,
                         double rho, double BA, void *S2_dev);
 
+/* Source of the n-th harmonic (2 <= n <= 9) from the lower harmonics, sum-
+ * frequency terms only (Sec. 2.1.4, the nonlinear wave equations with sum
+ * terms; Sec. 2.3.4, Eq. TBS_solution_nonlinear_shi_n):
+ *   S_n = -(1/2) xi (n omega)^2 sum_{a=1}^{n-1} psi_a psi_{n-a},
+ *   xi = (1 + B/2A) / (rho c^4), local sound speed c, omega the fundamental;
+ *   e.g. psi_1 psi_2 for n = 3, psi_2^2/2 + psi_1 psi_3 for n = 4.
+ *   fields_dev: host array of n-1 device pointers psi_1 .. psi_{n-1}, each
+ *               dev [B][P] plan dtype; c_dev: dev float64 [P];
+ *   S_dev: dev [B][P] plan dtype (may alias any field).
+ * Products and sums are formed in FP64 and rounded once.  n = 2 equals
+ * tbs_harmonic_source.  Errors: TBS_ERR_INVALID for n out of range, a NULL
+ * pointer or bad parameters. */
+int tbs_harmonic_source_n(tbs_plan *plan, int n, const void *const *fields_dev, const double *c_dev,
+                          double omega, double rho, double BA, void *S_dev);
+
 /* Gradient of Re<q, p_L> with respect to V for each right-hand side, i.e. the
  * adjoint of the truncated series:
  *   g_V = sum_{m=0}^{L-2} conj(w_m) * P_{L-1-m},  w_0 = G^H q,

@@ -290,6 +290,25 @@ def harmonic_source(p1: np.ndarray, c, omega: float, rho: float, BA: float) -> n
     return -0.5 * xi * (2.0 * omega) ** 2 * p1 * p1
 
 
+def harmonic_source_n(fields, n: int, c, omega: float, rho: float, BA: float) -> np.ndarray:
+    """Source of the n-th harmonic solve (n >= 2) from the lower harmonics
+    fields = [psi_1, ..., psi_{n-1}]: S_n = -xi (n omega)^2 * (1/2) sum over
+    a + b = n (a, b >= 1, ordered pairs) of psi_a psi_b, i.e. the sum-frequency
+    terms of Sec. 2.1.4 (Eqs. of the nonlinear wave equations with sum terms)
+    and Sec. 2.3.4 (Eq. TBS_solution_nonlinear_shi_n): psi_1 psi_2 for n = 3,
+    psi_2^2 / 2 + psi_1 psi_3 for n = 4, psi_2 psi_3 + psi_1 psi_4 for n = 5.
+    xi = (1 + B/(2A)) / (rho c^4) with the local c; omega is the fundamental."""
+    if n < 2 or len(fields) < n - 1:
+        raise ValueError("need psi_1 .. psi_{n-1}")
+    c = np.asarray(c, dtype=np.float64)
+    xi = (1.0 + 0.5 * BA) / (rho * c ** 4)
+    acc = np.zeros(np.broadcast(fields[0], c).shape, dtype=np.complex128)
+    for a in range(1, n):
+        b = n - a
+        acc = acc + fields[a - 1] * fields[b - 1]
+    return -xi * (n * omega) ** 2 * 0.5 * acc
+
+
 # ---------------------------------------------------------------- adjoint ---
 
 def receiver_misfit(p: np.ndarray, receivers: np.ndarray, p_obs: np.ndarray):

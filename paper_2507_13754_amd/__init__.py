@@ -31,7 +31,7 @@ EXPORTS = (
     "tbs_version", "tbs_status_string", "tbs_padded_length", "tbs_wavenumber",
     "tbs_background_k0", "tbs_hankel01", "tbs_self_cell", "tbs_plan_create", "tbs_plan_info",
     "tbs_plan_set_stream", "tbs_green_tabulate", "tbs_green_import", "tbs_green_export",
-    "tbs_potential", "tbs_solve", "tbs_harmonic_source", "tbs_adjoint", "tbs_misfit",
+    "tbs_potential", "tbs_solve", "tbs_harmonic_source", "tbs_harmonic_source_n", "tbs_adjoint", "tbs_misfit",
     "tbs_speed_gradient", "tbs_profile_enable", "tbs_profile_read", "tbs_plan_destroy",
     "tbs_last_error", "tbs_batch_create", "tbs_batch_solve", "tbs_batch_destroy",
     "tbs_batch_last_error", "tbs_plan_autotune",
@@ -84,6 +84,8 @@ def library() -> ctypes.CDLL:
         "tbs_green_export": (ctypes.c_int, [vp, vp]),
         "tbs_potential": (ctypes.c_int, [vp, vp] + [ctypes.c_double] * 5 + [vp, vp]),
         "tbs_solve": (ctypes.c_int, [vp, vp, vp, ctypes.c_int, vp, dp]),
+        "tbs_harmonic_source_n": (ctypes.c_int, [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_void_p), vp,
+                                                  ctypes.c_double, ctypes.c_double, ctypes.c_double, vp]),
         "tbs_harmonic_source": (ctypes.c_int, [vp, vp, vp, ctypes.c_double, ctypes.c_double,
                                                ctypes.c_double, vp]),
         "tbs_adjoint": (ctypes.c_int, [vp, vp, vp, ctypes.c_int, vp, vp, dp, ctypes.c_int]),
@@ -314,6 +316,22 @@ class Plan:
         self._sync_stream()
         _check(library().tbs_harmonic_source(self._h, pp, cp, omega, rho, BA, op), self._h,
                "tbs_harmonic_source")
+        return out
+
+    def harmonic_source_n(self, n: int, fields, c, omega: float, rho: float, BA: float, out=None):
+        """S_n from psi_1 .. psi_{n-1} (list of device tensors of the batch shape)."""
+        torch = _torch()
+        if len(fields) < n - 1:
+            raise ValueError("harmonic_source_n needs psi_1 .. psi_{n-1}")
+        ptrs = (ctypes.c_void_p * max(1, n - 1))(*[_ptr(f, self.dtype, self._bshape(), "field")
+                                                   for f in fields[: n - 1]])
+        cp = _ptr(c, torch.float64, self.shape, "c")
+        if out is None:
+            out = torch.empty(self._bshape(), dtype=self.dtype, device=fields[0].device)
+        op = _ptr(out, self.dtype, self._bshape(), "out")
+        self._sync_stream()
+        _check(library().tbs_harmonic_source_n(self._h, int(n), ptrs, cp, omega, rho, BA, op), self._h,
+               "tbs_harmonic_source_n")
         return out
 
     def adjoint(self, source, potential, nterms: int, adj_source, out=None,

@@ -953,6 +953,20 @@ int tbs_harmonic_source(tbs_plan* p, const void* p1, const double* c, double ome
   return TBS_OK;
 }
 
+int tbs_harmonic_source_n(tbs_plan* p, int n, const void* const* fields, const double* c,
+                          double omega, double rho, double BA, void* S) {
+  if (!p || !fields || !c || !S) return fail(p, TBS_ERR_INVALID, "NULL argument");
+  if (n < 2 || n > TBS_HARMONIC_MAX) return fail(p, TBS_ERR_INVALID, "harmonic order must be 2..9");
+  for (int a = 0; a < n - 1; ++a)
+    if (!fields[a]) return fail(p, TBS_ERR_INVALID, "NULL lower-harmonic field");
+  if (!(omega > 0) || !(rho > 0) || !is_fin(BA)) return fail(p, TBS_ERR_INVALID, "bad parameters");
+  const double nw = (double)n * omega;
+  const double coef = -0.5 * (1.0 + 0.5 * BA) / rho * nw * nw;
+  TBS_LAUNCH(p, tbs::launch_harmonic_source_n(n, fields, c, S, p->fp64, p->P, p->batch, coef,
+                                              p->stream));
+  return TBS_OK;
+}
+
 int tbs_adjoint(tbs_plan* p, const void* source, const void* V, int L, const void* q, void* grad,
                 double* residual_out, int flags) {
   int rc = check_plan_ready(p);

@@ -121,6 +121,10 @@ int launch_potential(const double* c, void* V, void* dVdc, bool fp64, int64_t n,
                      double a_abs, double disp, double k0sq_r, double k0sq_i, hipStream_t s);
 int launch_harmonic_source(const void* p1, const double* c, void* S2, bool fp64, int64_t n,
                            int nrhs, double coef, hipStream_t s);
+// highest harmonic order accepted by launch_harmonic_source_n
+#define TBS_HARMONIC_MAX 9
+int launch_harmonic_source_n(int n, const void* const* fields, const double* c, void* S, bool fp64,
+                             int64_t np, int nrhs, double coef, hipStream_t s);
 int launch_misfit(const void* p, const int64_t* rec, const void* p_obs, void* q, double* jpart,
                   bool fp64, int64_t P, int nrec, int nrhs, hipStream_t s);
 int launch_grad_assemble(const void* g, int nrhs, const void* dVdc, double* grad_c, bool fp64,

@@ -184,6 +184,49 @@ int launch_harmonic_source(const void* p1, const double* c, void* S2, bool fp64,
   return (int)hipGetLastError();
 }
 
+// n-th harmonic source from the lower harmonics (Sec. 2.3.4, Eqs. of the
+// nonlinear solutions with sum terms): S_n = coef / c^4 * sum_{a=1}^{n-1}
+// psi_a psi_{n-a} (ordered pairs, so the a = n-a term enters once), with
+// coef = -(1/2)(1 + B/2A)(n omega)^2 / rho; products and sum in FP64.
+struct HarmonicFields {
+  const void* f[TBS_HARMONIC_MAX - 1];
+};
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_harmonic_n(HarmonicFields h, int n, const double* c,
+                                                    cx<T>* S, int64_t np, int nrhs, double coef) {
+  const int64_t tot = np * nrhs;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double ar = 0.0, ai = 0.0;
+    for (int a = 1; a <= n / 2; ++a) {
+      const cx<T> x = ((const cx<T>*)h.f[a - 1])[i];
+      const cx<T> y = ((const cx<T>*)h.f[n - a - 1])[i];
+      const double w = (2 * a == n) ? 1.0 : 2.0;
+      ar += w * ((double)x.x * (double)y.x - (double)x.y * (double)y.y);
+      ai += w * ((double)x.x * (double)y.y + (double)x.y * (double)y.x);
+    }
+    const double ci = c[i % np];
+    const double g = coef / (ci * ci * ci * ci);
+    S[i] = cx<T>{(T)(g * ar), (T)(g * ai)};
+  }
+}
+
+int launch_harmonic_source_n(int n, const void* const* fields, const double* c, void* S, bool fp64,
+                             int64_t np, int nrhs, double coef, hipStream_t s) {
+  HarmonicFields h{};
+  for (int a = 0; a < n - 1; ++a) h.f[a] = fields[a];
+  const int64_t blocks = (np * nrhs + 255) / 256;
+  const dim3 g((unsigned)(blocks < 65536 * 8 ? blocks : 65536 * 8));
+  if (fp64)
+    hipLaunchKernelGGL(k_harmonic_n<double>, g, dim3(256), 0, s, h, n, c, (cx<double>*)S, np, nrhs,
+                       coef);
+  else
+    hipLaunchKernelGGL(k_harmonic_n<float>, g, dim3(256), 0, s, h, n, c, (cx<float>*)S, np, nrhs,
+                       coef);
+  return (int)hipGetLastError();
+}
+
 // Receiver misfit: r = p[b][rec] - p_obs[b][r]; q[b][rec] += r (q zeroed by
 // the caller; R^H sums receivers that share a cell); jpart[b][r] = |r|^2.
 template <typename T>

@@ -26,6 +26,12 @@
 #ifndef TBS_E_LONG_F32
 #define TBS_E_LONG_F32 16   // values per thread, FP32 lines of 2048+
 #endif
+#ifndef TBS_E_ODD_MUL_F32
+#define TBS_E_ODD_MUL_F32 8  // values per thread / odd radix, FP32 lines 3*2^a >= 384, 5*2^a >= 640
+#endif
+#ifndef TBS_SPLIT_ODD_E
+#define TBS_SPLIT_ODD_E 24   // odd-family lines with this many values per thread split re/im
+#endif
 #ifndef TBS_SPLIT_MIN
 #define TBS_SPLIT_MIN 1000000  // shortest line that exchanges re/im separately
 #endif
@@ -368,13 +374,13 @@ constexpr int odd_part(int M) {
 constexpr int elems_per_thread(int M, bool fp64) {
   const int r = odd_part(M);
   if (r == 1) return M <= 64 ? 4 : (M <= 512 ? 8 : ((M <= 1024 || fp64) ? 16 : TBS_E_LONG_F32));
-  if (!fp64 && ((r == 3 && M >= 384) || (r == 5 && M >= 640))) return 8 * r;
+  if (!fp64 && ((r == 3 && M >= 384) || (r == 5 && M >= 640))) return TBS_E_ODD_MUL_F32 * r;
   return 4 * r;
 }
 // Exchanges split into real and imaginary rounds (half the LDS per line) for
 // lines whose many values per thread would otherwise leave few lines per CU.
 constexpr bool split_lds(int M, bool fp64) {
-  return M >= TBS_SPLIT_MIN || (odd_part(M) > 1 && elems_per_thread(M, fp64) >= 24);
+  return M >= TBS_SPLIT_MIN || (odd_part(M) > 1 && elems_per_thread(M, fp64) >= TBS_SPLIT_ODD_E);
 }
 constexpr int rows_per_block(int M, bool fp64) {
   return fp64 ? (M >= 4096 ? TBS_NR_F64 : (M >= 2048 && !split_lds(M, true) ? 2 : 4))

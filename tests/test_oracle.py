@@ -315,6 +315,28 @@ def test_harmonic_source_from_time_domain():
     assert rel(S2, term) < 1e-12
 
 
+@pytest.mark.parametrize("n", [2, 3, 4, 5])
+def test_harmonic_source_n_from_time_domain(n):
+    """S_n equals the n omega Fourier component of xi d^2(Psi^2)/dt^2 for
+    Psi(t) = sum_{k<n} Re(psi_k e^{-i k omega t}) (no difference-frequency term
+    can reach n omega from harmonics below n), in the form lap psi + k^2 psi = -S."""
+    omega, rho, BA = 2 * np.pi * 1e6, 1000.0, 5.0
+    rng = np.random.default_rng(70 + n)
+    c = np.array([1480.0, 1500.0, 1575.0, 1620.0])
+    fields = [(rng.standard_normal(4) + 1j * rng.standard_normal(4)) * 10 ** (5 - k) for k in range(n - 1)]
+    nt = 64
+    t = np.arange(nt) * (2 * np.pi / omega) / nt
+    Psi = sum(np.real(f[:, None] * np.exp(-1j * (k + 1) * omega * t[None, :])) for k, f in enumerate(fields))
+    xi = (1 + BA / 2) / (rho * c ** 4)
+    spec = np.fft.fft(Psi ** 2, axis=1) / nt
+    Xn = 2 * spec[:, nt - n]                      # amplitude of e^{-i n omega t}
+    term = xi * (-(n * omega) ** 2) * Xn
+    S = oracle.harmonic_source_n(fields, n, c, omega, rho, BA)
+    assert rel(S, term) < 1e-12
+    if n == 2:
+        assert rel(S, oracle.harmonic_source(fields[0], c, omega, rho, BA)) < 1e-15
+
+
 # ---------------------------------------------------------------- adjoint ---
 
 def test_adjoint_green_operator_dot_product():
