@@ -1,5 +1,9 @@
-// Host-side check library (tests only): exposes the radix butterflies of
-// tbs_fft.hpp to the CPU test-suite.  Not part of libtbs.
+// Host-side check library (tests only): exposes the radix butterflies, the
+// stage plans and the exchange index maps of tbs_fft.hpp to the CPU
+// test-suite.  Not part of libtbs.
+#include <cmath>
+#include <vector>
+
 #include "../tbs_fft.hpp"
 
 namespace {
@@ -31,4 +35,88 @@ extern "C" int tbs_hostcheck_stages(int M, int E, int* radices) {
   tbs::Stages s = tbs::make_stages(M, E);
   for (int i = 0; i < s.n; ++i) radices[i] = s.r[i];
   return s.n;
+}
+
+namespace {
+template <int R, bool INV>
+void dft_n(tbs::cx<double>* a) {
+  tbs::cx<double> b[R];
+  for (int i = 0; i < R; ++i) b[i] = a[i];
+  tbs::dft<R, INV>(b);
+  for (int i = 0; i < R; ++i) a[i] = b[i];
+}
+
+template <bool INV>
+void dft_rt(int R, tbs::cx<double>* a) {
+  switch (R) {
+    case 2: dft_n<2, INV>(a); break;
+    case 3: dft_n<3, INV>(a); break;
+    case 4: dft_n<4, INV>(a); break;
+    case 5: dft_n<5, INV>(a); break;
+    case 8: dft_n<8, INV>(a); break;
+    case 16: dft_n<16, INV>(a); break;
+  }
+}
+}  // namespace
+
+// Runs the device transform's data flow on the host: TPT = M/E emulated
+// threads with E registers each in the strided layout, every stage's
+// butterflies, and between stages either the exchange through a shared
+// array (stage_out_index, read back strided) or, for local stages, the
+// register renaming local_register.  out receives the transform (natural
+// order); *n_exchanges / *n_local count the two kinds of hand-over.
+extern "C" int tbs_hostcheck_fft(int M, int E, int inv, const double* in, double* out,
+                                 int* n_exchanges, int* n_local) {
+  if (M % E) return -1;
+  const tbs::Stages st = tbs::make_stages(M, E);
+  if (st.n <= 0) return -1;
+  const int TPT = M / E;
+  std::vector<tbs::cx<double>> v((size_t)M), w((size_t)M), sh((size_t)M);
+  for (int t = 0; t < TPT; ++t)
+    for (int j = 0; j < E; ++j) v[(size_t)t * E + j] = {in[2 * (t + j * TPT)], in[2 * (t + j * TPT) + 1]};
+  int L = 1;
+  *n_exchanges = 0;
+  *n_local = 0;
+  const double sgn = inv ? 1.0 : -1.0;
+  for (int S = 0; S < st.n; ++S) {
+    const int R = st.r[S];
+    const int NB = E / R;
+    const bool last = S + 1 == st.n;
+    const bool local = tbs::stage_is_local(M, E, S);
+    for (int t = 0; t < TPT; ++t) {
+      for (int q = 0; q < NB; ++q) {
+        const int b = t + q * TPT;
+        const int k = b % L;
+        tbs::cx<double> a[16];
+        for (int r = 0; r < R; ++r) {
+          a[r] = v[(size_t)t * E + q + r * NB];
+          if (S > 0 && r > 0) {
+            const double ang = sgn * 2.0 * M_PI * (double)(r * k) / (double)(L * R);
+            a[r] = tbs::cmul(a[r], tbs::cx<double>{std::cos(ang), std::sin(ang)});
+          }
+        }
+        if (inv) dft_rt<true>(R, a); else dft_rt<false>(R, a);
+        for (int r = 0; r < R; ++r) {
+          if (last) w[(size_t)t * E + q + r * NB] = a[r];
+          else if (local) w[(size_t)t * E + tbs::local_register(q, r, TPT, L, R)] = a[r];
+          else sh[(size_t)tbs::stage_out_index(b, L, R, r)] = a[r];
+        }
+      }
+    }
+    if (!last && !local) {
+      for (int t = 0; t < TPT; ++t)
+        for (int j = 0; j < E; ++j) w[(size_t)t * E + j] = sh[(size_t)(t + j * TPT)];
+      ++*n_exchanges;
+    } else if (local) {
+      ++*n_local;
+    }
+    v.swap(w);
+    L *= R;
+  }
+  for (int t = 0; t < TPT; ++t)
+    for (int j = 0; j < E; ++j) {
+      out[2 * (t + j * TPT)] = v[(size_t)t * E + j].x;
+      out[2 * (t + j * TPT) + 1] = v[(size_t)t * E + j].y;
+    }
+  return 0;
 }

@@ -266,6 +266,22 @@ __host__ __device__ constexpr int stage_twoff(int M, int E, int S) {
   return off;
 }
 
+// Index of output r of butterfly b in a stage of radix R and span L.
+__host__ __device__ constexpr int stage_out_index(int b, int L, int R, int r) {
+  return (b / L) * L * R + b % L + r * L;
+}
+
+// When L is a multiple of TPT (a stage after which every thread reads back
+// exactly the values it wrote): the register j' that receives output r of the
+// thread's butterfly q, i.e. (stage_out_index(t + q TPT, L, R, r) - t) / TPT.
+__host__ __device__ constexpr int local_register(int q, int r, int TPT, int L, int R) {
+  return (TPT * q / L) * (L * R / TPT) + (TPT * q) % L / TPT + r * (L / TPT);
+}
+
+__host__ __device__ constexpr bool stage_is_local(int M, int E, int S) {
+  return S + 1 < make_stages(M, E).n && stage_L(M, E, S) % (M / E) == 0;
+}
+
 // LDS index with one pad slot per 16 elements (breaks power-of-two strides).
 __device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
 __host__ __device__ constexpr int lds_len(int M) { return M + M / 16 + 4; }
@@ -285,6 +301,11 @@ __device__ __forceinline__ void fft_stages(cx<T> (&v)[E], void* __restrict__ shv
   constexpr int NB = E / R;
   constexpr int OFF = stage_twoff(M, E, S);
   constexpr bool LAST = (S + 1 == st.n);
+  // Once L is a multiple of TPT, output r of butterfly b = t + q TPT lands on
+  // index t + j' TPT with j' fixed by (q, r): the reader is the writing thread
+  // itself, so the exchange is a register renaming (no LDS, no barrier).
+  constexpr bool LOCAL = stage_is_local(M, E, S);
+  cx<T> w[LOCAL ? E : 1];
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
     const int b = t + q * TPT;
@@ -300,25 +321,31 @@ __device__ __forceinline__ void fft_stages(cx<T> (&v)[E], void* __restrict__ shv
       }
     }
     dft<R, INV>(a);
-    if constexpr (LAST || SPLIT) {
+    if constexpr (LOCAL) {
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        w[local_register(q, r, TPT, L, R)] = a[r];
+    } else if constexpr (LAST || SPLIT) {
 #pragma unroll
       for (int r = 0; r < R; ++r) v[q + r * NB] = a[r];
     } else {
       cx<T>* sh = (cx<T>*)shv;
-      const int base = (b / L) * L * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) sh[lpad(base + r * L)] = a[r];
+      for (int r = 0; r < R; ++r) sh[lpad(stage_out_index(b, L, R, r))] = a[r];
     }
   }
-  if constexpr (!LAST) {
+  if constexpr (LOCAL) {
+#pragma unroll
+    for (int j = 0; j < E; ++j) v[j] = w[j];
+    fft_stages<T, M, E, INV, SPLIT, S + 1>(v, shv, tw, t);
+  } else if constexpr (!LAST) {
     if constexpr (SPLIT) {
       T* sh = (T*)shv;
 #pragma unroll
       for (int q = 0; q < NB; ++q) {
         const int b = t + q * TPT;
-        const int base = (b / L) * L * R + (b % L);
 #pragma unroll
-        for (int r = 0; r < R; ++r) sh[lpad(base + r * L)] = v[q + r * NB].x;
+        for (int r = 0; r < R; ++r) sh[lpad(stage_out_index(b, L, R, r))] = v[q + r * NB].x;
       }
       __syncthreads();
 #pragma unroll
@@ -327,9 +354,8 @@ __device__ __forceinline__ void fft_stages(cx<T> (&v)[E], void* __restrict__ shv
 #pragma unroll
       for (int q = 0; q < NB; ++q) {
         const int b = t + q * TPT;
-        const int base = (b / L) * L * R + (b % L);
 #pragma unroll
-        for (int r = 0; r < R; ++r) sh[lpad(base + r * L)] = v[q + r * NB].y;
+        for (int r = 0; r < R; ++r) sh[lpad(stage_out_index(b, L, R, r))] = v[q + r * NB].y;
       }
       __syncthreads();
 #pragma unroll

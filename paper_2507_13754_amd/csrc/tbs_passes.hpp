@@ -27,7 +27,7 @@
 #define TBS_E_LONG_F32 16   // values per thread, FP32 lines of 2048+
 #endif
 #ifndef TBS_E_ODD_MUL_F32
-#define TBS_E_ODD_MUL_F32 8  // values per thread / odd radix, FP32 lines 3*2^a >= 384, 5*2^a >= 640
+#define TBS_E_ODD_MUL_F32 4  // values per thread / odd radix, FP32 lines 3*2^a >= 384, 5*2^a >= 640
 #endif
 #ifndef TBS_SPLIT_ODD_E
 #define TBS_SPLIT_ODD_E 24   // odd-family lines with this many values per thread split re/im
@@ -47,8 +47,8 @@
 #ifndef TBS_NC_F64
 #define TBS_NC_F64 2        // columns per FP64 column-convolution block (lines of 2048+)
 #endif
-#ifndef TBS_MIN_WAVES
-#define TBS_MIN_WAVES 0     // occupancy hint for the long-line passes (0: none)
+#ifndef TBS_OCC_HINT
+#define TBS_OCC_HINT 1      // size each pass's register budget to its LDS occupancy
 #endif
 
 namespace tbs {
@@ -295,9 +295,34 @@ __device__ __forceinline__ void col_pass_body(const ColArgs& a, const int lb) {
   }
 }
 
+// Resident waves per SIMD a pass asks the compiler to budget registers for
+// (512 VGPRs per SIMD lane, shared by its waves): what the LDS of one block
+// (LINES lines of length M; 160 KB per CU, 4 SIMDs, at most 8 waves each)
+// allows, but no more than a line of E values per thread can keep in
+// registers without spilling (about 5 E + 40 VGPRs in FP32, twice the values
+// in FP64, at least 112).  Without the request, lines of 40 values per
+// thread compiled to more than 256 VGPRs: one wave per SIMD.
+template <typename T>
+constexpr int lds_waves_per_eu(int M, int E, int lines, bool split) {
+  if (!TBS_OCC_HINT) return 1;
+  const long lds = (long)lines * lds_len(M) * (long)(split ? sizeof(T) : 2 * sizeof(T));
+  const int waves_blk = (lines * (M / E) + 63) / 64;
+  long blocks = (160L * 1024) / lds;
+  if (blocks * waves_blk > 32) blocks = 32 / waves_blk;
+  int w = (int)(blocks * waves_blk / 4);
+  const int need = (sizeof(T) == 8 ? 10 : 5) * E + 40;
+  const int regs = need < 112 ? 112 : need;
+  const int wr = 512 / regs;
+  if (w > wr) w = wr;
+  return w < 1 ? 1 : (w > 8 ? 8 : w);
+}
+
+#define TBS_OCCUPANCY(T, M, E, LINES, SPLIT) \
+  __attribute__((amdgpu_waves_per_eu(lds_waves_per_eu<T>(M, E, LINES, SPLIT), 8)))
+
 // Plain in-place FFT of contiguous rows [nrows][M] (tabulation, FP64).
 template <typename T, int M, int E, int NR, bool SPLIT>
-__global__ void __launch_bounds__(NR * (M / E)) k_row_fft_full(cx<T>* data, const cx<T>* tw,
+__global__ void __launch_bounds__(NR * (M / E)) TBS_OCCUPANCY(T, M, E, NR, SPLIT) k_row_fft_full(cx<T>* data, const cx<T>* tw,
                                                                int nrows, int inverse) {
   constexpr int TPT = M / E;
   constexpr int LD = lds_len(M);
@@ -325,12 +350,12 @@ __global__ void __launch_bounds__(NR * (M / E)) k_row_fft_full(cx<T>* data, cons
 // ---------------------------------------------------------------- kernels --
 
 template <typename T, int M, int E, int NR, int CB, bool SPLIT>
-__global__ void __launch_bounds__(NR * (M / E)) k_row_pass(RowArgs a) {
+__global__ void __launch_bounds__(NR * (M / E)) TBS_OCCUPANCY(T, M, E, NR, SPLIT) k_row_pass(RowArgs a) {
   row_pass_body<T, M, E, NR, CB, SPLIT>(a, xcd_block(blockIdx.x, gridDim.x, a.xcd_remap));
 }
 
 template <typename T, int M, int E, int NC, int OP, bool SPLIT>
-__global__ void __launch_bounds__(NC * (M / E)) k_col_pass(ColArgs a) {
+__global__ void __launch_bounds__(NC * (M / E)) TBS_OCCUPANCY(T, M, E, NC, SPLIT) k_col_pass(ColArgs a) {
   col_pass_body<T, M, E, NC, OP, SPLIT>(a, xcd_block(blockIdx.x, gridDim.x, a.xcd_remap));
 }
 
@@ -343,7 +368,8 @@ __device__ __forceinline__ int group_of(const int* __restrict__ starts, int ngro
 }
 
 template <typename T, int M, int E, int NR, int CB, bool SPLIT>
-__global__ void __launch_bounds__(NR * (M / E)) k_row_pass_group(const RowArgs* __restrict__ descs,
+__global__ void __launch_bounds__(NR * (M / E)) TBS_OCCUPANCY(T, M, E, NR, SPLIT)
+    k_row_pass_group(const RowArgs* __restrict__ descs,
                                                                  const int* __restrict__ starts,
                                                                  int ngroups) {
   const int b = xcd_block(blockIdx.x, gridDim.x, 1);
@@ -352,7 +378,8 @@ __global__ void __launch_bounds__(NR * (M / E)) k_row_pass_group(const RowArgs* 
 }
 
 template <typename T, int M, int E, int NC, int OP, bool SPLIT>
-__global__ void __launch_bounds__(NC * (M / E)) k_col_pass_group(const ColArgs* __restrict__ descs,
+__global__ void __launch_bounds__(NC * (M / E)) TBS_OCCUPANCY(T, M, E, NC, SPLIT)
+    k_col_pass_group(const ColArgs* __restrict__ descs,
                                                                  const int* __restrict__ starts,
                                                                  int ngroups) {
   const int b = xcd_block(blockIdx.x, gridDim.x, 1);
@@ -369,8 +396,10 @@ constexpr int odd_part(int M) {
 }
 
 // Values per thread.  Powers of two: 4 / 8 / 16 by length (FP32 lines of
-// 2048+ use TBS_E_LONG_F32).  3 * 2^a and 5 * 2^a: 8 * odd part for FP32
-// lines of 384+ / 640+ (radix-8 stages then one odd stage), else 4 * odd part.
+// 2048+ use TBS_E_LONG_F32).  3 * 2^a and 5 * 2^a: 4 * odd part (radix-4
+// stages, one radix-2 if needed, one odd stage); FP32 lines of 384+ / 640+
+// use TBS_E_ODD_MUL_F32 * odd part (8: radix-8 stages, fewer exchanges but
+// twice the registers and one wave per line).
 constexpr int elems_per_thread(int M, bool fp64) {
   const int r = odd_part(M);
   if (r == 1) return M <= 64 ? 4 : (M <= 512 ? 8 : ((M <= 1024 || fp64) ? 16 : TBS_E_LONG_F32));

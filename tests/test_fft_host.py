@@ -40,3 +40,29 @@ def test_stage_plan(hc, M, E):
     radices = [r[i] for i in range(n)]
     assert n > 0 and int(np.prod(radices)) == M
     assert all(E % x == 0 for x in radices)
+
+
+@pytest.mark.parametrize("M,E", [(16, 4), (48, 12), (96, 12), (160, 20), (320, 20), (640, 40), (768, 24),
+                                 (1280, 40), (1536, 24), (2048, 16), (2560, 40), (2560, 20), (3072, 24),
+                                 (4096, 16)])
+@pytest.mark.parametrize("inv", [0, 1])
+def test_stage_data_flow_is_a_dft(hc, M, E, inv):
+    """The device transform's hand-over between stages (shared-array exchange
+    or in-thread register renaming), emulated on the host, gives the DFT."""
+    rng = np.random.default_rng(M + E + inv)
+    x = rng.standard_normal(M) + 1j * rng.standard_normal(M)
+    inp = np.ascontiguousarray(np.stack([x.real, x.imag], 1).ravel())
+    out = np.zeros(2 * M)
+    nex, nloc = ctypes.c_int(), ctypes.c_int()
+    assert hc.tbs_hostcheck_fft(M, E, inv, inp.ctypes.data_as(ctypes.c_void_p),
+                                out.ctypes.data_as(ctypes.c_void_p), ctypes.byref(nex), ctypes.byref(nloc)) == 0
+    y = out[0::2] + 1j * out[1::2]
+    ref = np.fft.ifft(x) * M if inv else np.fft.fft(x)
+    assert np.max(np.abs(y - ref)) < 1e-13 * np.max(np.abs(ref))
+    # every stage but the last hands over once; lines with 4+ stages keep the
+    # hand-overs after L reaches M/E inside the thread
+    r = (ctypes.c_int * 12)()
+    n = hc.tbs_hostcheck_stages(M, E, r)
+    assert nex.value + nloc.value == n - 1
+    if n >= 4:
+        assert nloc.value >= 1

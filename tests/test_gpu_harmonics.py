@@ -40,7 +40,7 @@ def test_harmonics_up_to_fifth(dev, dt, shape):
     a0, y = workloads.alpha0_si(0.75, 1.5), 1.5
     rho, BA = workloads.RHO0, 5.0
     s = np.zeros((1,) + shape, np.complex128)
-    s[(0,) + tuple(n // 3 for n in shape)] = 1.0 / dx ** len(shape)
+    s[(0,) + tuple(n // 3 for n in shape)] = 1e6 / dx ** 2    # p1 ~ 1e5 Pa (far from FP32 limits)
     L = 5
     # oracle chain
     ref = []
@@ -58,14 +58,13 @@ def test_harmonics_up_to_fifth(dev, dt, shape):
             src = torch.from_numpy(s).to(dev, tdt(dt))
         else:
             src = plan.harmonic_source_n(n, got, cd, om, rho, BA)
-            S_ref = oracle.harmonic_source_n([r for r in ref], n, c, om, rho, BA)
             S_dev = oracle.harmonic_source_n([g.cpu().numpy().astype(np.complex128) for g in got],
                                              n, c, om, rho, BA)
             # the source kernel itself, on the device's own lower harmonics
             assert rel(src.cpu().numpy(), S_dev) <= (1e-14 if dt == "c128" else 1e-6)
         got.append(plan.solve(src, plan.potential(cd, n * om, workloads.C0, a0, y), L))
         plan.close()
-        assert rel(got[-1].cpu().numpy(), ref[-1]) <= TOL[dt] * 3, n
+        assert rel(got[-1].cpu().numpy(), ref[n - 1]) <= TOL[dt] * 3, n
     assert all(np.linalg.norm(r) > 0 for r in ref)
 
 
