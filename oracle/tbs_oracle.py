@@ -22,7 +22,15 @@ What it computes (citations are to the paper's sections and equations):
 * dense Lippmann-Schwinger solves and the spectral radius of G V
   (Sec. 2.2, convergence condition under Eq. TBS_2);
 * the second-harmonic source -xi (2 omega)^2 p1^2 / 2 (Sec. 2.1.4
-  Eq. nonlinear_waveeqn_shi2; Sec. 2.3.4 Eq. TBS_solution_shi_2);
+  Eq. nonlinear_waveeqn_shi2; Sec. 2.3.4 Eq. TBS_solution_shi_2) and the
+  sum-frequency sources of harmonics 3..5 (Sec. 2.3.4,
+  Eq. TBS_solution_nonlinear_shi_n);
+* the paper's own periodic scheme (Sec. 2.2 Eq. of g~, Sec. 3.1 and
+  Algorithm 1): g~(p) = 1/(|p|^2 - k^2 - i eps) on the unpadded grid, the
+  spatial potential (Cases I, III, IV) or the k-space potential of the
+  absorbing-dispersive medium (Case II, Sec. 2.3.2), the sigmoid absorbing
+  layer applied after every iteration but the first (Eq. ABL_profile), and
+  the centre-row relative L1 change as stopping error (Eq. Error);
 * the exact gradient of a receiver misfit of the truncated series with
   respect to the sound speed (the adjoint of the series; not in the paper).
 
@@ -307,6 +315,84 @@ def harmonic_source_n(fields, n: int, c, omega: float, rho: float, BA: float) ->
         b = n - a
         acc = acc + fields[a - 1] * fields[b - 1]
     return -xi * (n * omega) ** 2 * 0.5 * acc
+
+
+# ------------------------------------------------- periodic (paper) mode ---
+
+def periodic_green_spectrum(k: complex, eps: float, dx: float, shape: Sequence[int]) -> np.ndarray:
+    """g~(p) = 1 / (|p|^2 - k^2 - i eps) on the FFT grid of ``shape`` (C order,
+    last axis fastest) with p = 2 pi m / (n dx), m the signed FFT index
+    (Sec. 2.2, the Fourier transform of g; Algorithm 1's table after its
+    fftShift)."""
+    axes = [2.0 * np.pi * np.fft.fftfreq(n, d=dx) for n in shape]
+    grids = np.meshgrid(*axes, indexing="ij")
+    p2 = sum(g * g for g in grids)
+    return 1.0 / (p2 - complex(k) ** 2 - 1j * eps)
+
+
+def kspace_potential(dx: float, shape: Sequence[int], omega: float, tau: float, eta: float,
+                     nu: float, eps: float) -> np.ndarray:
+    """Case II potential in k-space, VV(p) = eta |p|^(nu+1) - i (tau omega
+    |p|^nu + eps) (Sec. 2.3.2 Eq. TBS_solution_absorbing-dispersive; the
+    fractional Laplacians become powers of |p|)."""
+    axes = [2.0 * np.pi * np.fft.fftfreq(n, d=dx) for n in shape]
+    grids = np.meshgrid(*axes, indexing="ij")
+    kmod = np.sqrt(sum(g * g for g in grids))
+    return eta * kmod ** (nu + 1.0) - 1j * (tau * omega * kmod ** nu + eps)
+
+
+def tau_eta(alpha0: float, nu: float, c: float) -> Tuple[float, float]:
+    """tau = -2 alpha0 c^(nu-1), eta = 2 alpha0 c^nu tan(pi nu / 2) (Sec. 2.1.2,
+    the absorption and dispersion proportionality coefficients)."""
+    return -2.0 * alpha0 * c ** (nu - 1.0), 2.0 * alpha0 * c ** nu * math.tan(math.pi * nu / 2.0)
+
+
+def abl_profile(n: int, dx: float, zeta_np_per_cm: float, mu_cells: float) -> np.ndarray:
+    """Sigmoid absorbing layer along one axis (Sec. 3.1 Eq. ABL_profile):
+    f = 1 / (1 + exp(-zeta (x - mu / 2))) inside a layer of width mu at either
+    end, x the distance in cm of the cell from the nearer outer edge; 1
+    elsewhere."""
+    i = np.arange(n, dtype=np.float64)
+    d_cm = np.minimum(i, n - 1 - i) * dx * 100.0
+    mu_cm = mu_cells * dx * 100.0
+    f = 1.0 / (1.0 + np.exp(-zeta_np_per_cm * (d_cm - 0.5 * mu_cm)))
+    return np.where(d_cm < mu_cm, f, 1.0)
+
+
+def abl_mask(shape: Sequence[int], dx: float, zeta_np_per_cm: float, mu_cells: float) -> np.ndarray:
+    """Absorbing-layer mask on a 2D grid: the product of the per-axis profiles."""
+    ny, nx = shape
+    return np.outer(abl_profile(ny, dx, zeta_np_per_cm, mu_cells), abl_profile(nx, dx, zeta_np_per_cm, mu_cells))
+
+
+def paper_iterate(gtilde: np.ndarray, s: np.ndarray, V: Optional[np.ndarray] = None,
+                  VV: Optional[np.ndarray] = None, mask: Optional[np.ndarray] = None,
+                  check_row: Optional[int] = None, tol: float = 1e-5, max_iter: int = 2000):
+    """The paper's iteration (Algorithm 1, one right-hand side ``s``):
+    psi_in = ifft(g~ fft(S)); then repeatedly
+      Cases I, III, IV: psi_fn = ifft(g~ fft(V psi_in + S)) * ABL,
+      Case II:          psi_fn = ifft(g~ (VV fft(psi_in) + fft(S))) * ABL,
+    the error = sum_m |psi_fn[c, m] - psi_in[c, m]| / sum_m |psi_in[c, m]| on
+    the check row c (Sec. 3.1 Eq. Error), stopping at the first iteration
+    whose error is below ``tol`` (the returned count) or after ``max_iter``.
+    Returns (psi, iterations, errors)."""
+    S = np.fft.fft2(s)
+    psi = np.fft.ifft2(gtilde * S)
+    c = s.shape[0] // 2 if check_row is None else check_row
+    errs = []
+    for it in range(1, max_iter + 1):
+        if VV is not None:
+            new = np.fft.ifft2(gtilde * (VV * np.fft.fft2(psi) + S))
+        else:
+            new = np.fft.ifft2(gtilde * np.fft.fft2((V if V is not None else 0.0) * psi + s))
+        if mask is not None:
+            new = new * mask
+        err = float(np.sum(np.abs(new[c] - psi[c])) / np.sum(np.abs(psi[c])))
+        errs.append(err)
+        psi = new
+        if err < tol:
+            return psi, it, np.array(errs)
+    return psi, max_iter, np.array(errs)
 
 
 # ---------------------------------------------------------------- adjoint ---

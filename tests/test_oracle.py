@@ -337,6 +337,98 @@ def test_harmonic_source_n_from_time_domain(n):
         assert rel(S, oracle.harmonic_source(fields[0], c, omega, rho, BA)) < 1e-15
 
 
+# ---------------------------------------------------- periodic (paper) mode --
+
+def test_periodic_green_kernel_is_the_lossy_hankel_function():
+    """ifft(g~)/dx^2 on a large periodic grid approaches the free-space 2D
+    Green's function (i/4) H0(kappa r), kappa^2 = k^2 + i eps (the eps-lossy
+    equation of Sec. 2.2), with second-order convergence in dx: pins the sign
+    and the normalisation of g~ and the p-grid."""
+    import scipy.special
+    lam = 1.0
+    k = 2 * np.pi / lam
+    eps = 0.8 * k * k
+    kap = np.sqrt(k * k + 1j * eps)
+    errs = []
+    for ppw in (10, 20, 40):
+        dx = lam / ppw
+        n = 32 * ppw // 10 * 8
+        ker = np.fft.ifft2(oracle.periodic_green_spectrum(k, eps, dx, (n, n))) / dx ** 2
+        cells = [int(round(r * ppw)) for r in (0.4, 0.8)]   # r = 0.4 and 0.8 wavelengths
+        e = max(abs(ker[0, m] - 0.25j * scipy.special.hankel1(0, kap * m * dx)) /
+                abs(0.25j * scipy.special.hankel1(0, kap * m * dx)) for m in cells)
+        errs.append(e)
+    assert errs[1] < 0.5 * errs[0] and errs[2] < 0.5 * errs[1], errs
+    assert errs[2] < 3e-3, errs
+
+
+def _periodic_case(n=24, seed=3):
+    dx = 1.0
+    k = 2 * np.pi / 6.3       # between grid wavenumbers
+    eps = 0.8 * k * k
+    s = workloads.random_field((n, n), seed)
+    return dx, k, eps, s
+
+
+@pytest.mark.parametrize("L", [1, 2, 7])
+def test_paper_iteration_constant_potential_closed_form(L):
+    """Case I with a constant V and no absorbing layer: the iteration is
+    diagonal in k-space, psi^L = ifft(g~ S (1 - (g~ V)^(L+1)) / (1 - g~ V))
+    (the geometric partial sum of the series, Sec. 2.2 Eq. TBS_2)."""
+    dx, k, eps, s = _periodic_case()
+    g = oracle.periodic_green_spectrum(k, eps, dx, s.shape)
+    V = -1j * eps + 0.1 * k * k
+    psi, it, errs = oracle.paper_iterate(g, s, V=np.full(s.shape, V), tol=0.0, max_iter=L)
+    q = g * V
+    ref = np.fft.ifft2(g * np.fft.fft2(s) * (1 - q ** (L + 1)) / (1 - q))
+    assert it == L and len(errs) == L
+    assert rel(psi, ref) < 1e-12
+
+
+def test_paper_iteration_kspace_potential_closed_form():
+    """Case II: psi^L = ifft(g~ S (1 - (g~ VV)^(L+1)) / (1 - g~ VV)) with the
+    k-space potential of the absorbing-dispersive medium."""
+    dx, k, eps, s = _periodic_case(seed=5)
+    g = oracle.periodic_green_spectrum(k, eps, dx, s.shape)
+    tau, eta = oracle.tau_eta(5.5e-10, 1.5, 1500.0)
+    # a medium 1e3 times more lossy than tissue keeps the test sensitive to VV
+    VV = oracle.kspace_potential(dx, s.shape, 2 * np.pi * 1e6, 1e3 * tau, 1e3 * eta, 1.5, eps)
+    psi, it, _ = oracle.paper_iterate(g, s, VV=VV, tol=0.0, max_iter=5)
+    q = g * VV
+    ref = np.fft.ifft2(g * np.fft.fft2(s) * (1 - q ** 6) / (1 - q))
+    assert rel(psi, ref) < 1e-12
+
+
+def test_paper_iteration_converges_to_lossless_periodic_solution():
+    """With V = -i eps the eps-shift cancels at convergence: psi solves the
+    lossless periodic Helmholtz equation, psi^ = S^ / (|p|^2 - k^2)
+    (Sec. 2.3.1 Eq. TBS_solution_lossless)."""
+    dx, k, eps, s = _periodic_case(n=16, seed=7)
+    g = oracle.periodic_green_spectrum(k, eps, dx, s.shape)
+    psi, it, errs = oracle.paper_iterate(g, s, V=np.full(s.shape, -1j * eps), tol=1e-13, max_iter=20000)
+    axes = [2 * np.pi * np.fft.fftfreq(n, d=dx) for n in s.shape]
+    P2 = axes[0][:, None] ** 2 + axes[1][None, :] ** 2
+    ref = np.fft.ifft2(np.fft.fft2(s) / (P2 - k * k))
+    assert it < 20000 and rel(psi, ref) < 1e-9
+
+
+def test_abl_profile_shape():
+    """Eq. ABL_profile with the paper's zeta = 21.48 Np/cm and mu = 450 dx at
+    dx = 20 um: 1/2 at mu/2 from the edge, rising through the layer, 1
+    beyond it, and the 2D mask is the product of the axis profiles."""
+    dx, zeta, mu = 20e-6, 21.48, 450
+    n = 1200
+    f = oracle.abl_profile(n, dx, zeta, mu)
+    assert f[225] == pytest.approx(0.5, abs=1e-15)
+    assert f[n - 1 - 225] == pytest.approx(0.5, abs=1e-15)
+    assert np.all(np.diff(f[:450]) > 0)
+    assert np.all(f[450:n - 450] == 1.0)
+    assert f[0] == pytest.approx(1.0 / (1.0 + math.exp(zeta * 0.45)), rel=1e-12)
+    m = oracle.abl_mask((n, 1000), dx, zeta, mu)
+    assert m[225, 500] == pytest.approx(0.5) and m[600, 450] == 1.0
+    assert m[225, 225] == pytest.approx(0.25)
+
+
 # ---------------------------------------------------------------- adjoint ---
 
 def test_adjoint_green_operator_dot_product():
