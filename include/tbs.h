@@ -55,8 +55,17 @@ enum tbs_status {
   TBS_ERR_HIP = -4,         /* a HIP runtime call failed */
   TBS_ERR_STATE = -5,       /* call out of order (e.g. solve before tabulate) */
   TBS_WARN_NONFINITE = 1,   /* a residual is NaN/Inf (non-finite input?) */
-  TBS_WARN_DIVERGING = 2    /* residuals grew over 3 consecutive terms */
+  TBS_WARN_DIVERGING = 2,   /* residuals grew over 3 consecutive terms */
+  TBS_WARN_NOT_CONVERGED = 3 /* tbs_iterate reached max_iter above the tolerance */
 };
+
+/* Case II potential of the paper's periodic scheme in k-space (Sec. 2.3.2,
+ * Eq. TBS_solution_absorbing-dispersive): VV(p) = eta |p|^(nu+1)
+ * - i (tau omega |p|^nu + eps), tau = -2 alpha0 c^(nu-1),
+ * eta = 2 alpha0 c^nu tan(pi nu / 2) (Sec. 2.1.2). */
+typedef struct {
+  double tau, eta, nu, omega;
+} tbs_kspace_potential;
 
 enum tbs_adjoint_flags {
   TBS_ADJ_STORE = 0,     /* keep all L-1 forward partial sums in HBM */
@@ -103,7 +112,12 @@ int tbs_self_cell(int ndim, tbs_c128 k0, double dx, tbs_c128 *w0_out);
  *   grid[3]   : N_x, N_y, N_z physical points (grid[2] ignored when ndim=2)
  *   dx        : cell size [m], > 0
  *   k0        : complex background wavenumber, Re k0 > 0, Im k0 >= 0
- *   padding   : >= 2; padded length per axis = tbs_padded_length(N, padding)
+ *   padding   : >= 2; padded length per axis = tbs_padded_length(N, padding).
+ *               1: a periodic plan of the paper's own scheme (no padding,
+ *               M = N; 2D, N_x and N_y powers of two in [16, 4096], else
+ *               TBS_ERR_UNSUPPORTED), used by tbs_green_periodic and
+ *               tbs_iterate only (the padded-series calls return
+ *               TBS_ERR_STATE on it; k0 is the k of g~)
  *   dtype     : TBS_C64 or TBS_C128 (precision of the series)
  *   batch     : B >= 1 right-hand sides per solve (they share V and G)
  *   hip_stream: hipStream_t to queue work on (NULL = the null stream)
@@ -184,6 +198,56 @@ int tbs_harmonic_source(tbs_plan *plan, const void *p1_dev, const double *c_dev,
  * pointer or bad parameters. */
 int tbs_harmonic_source_n(tbs_plan *plan, int n, const void *const *fields_dev, const double *c_dev,
                           double omega, double rho, double BA, void *S_dev);
+
+/* ---- the paper's periodic scheme (periodic plans, padding 1) ----------- */
+
+/* Tabulate the periodic spectrum g~(p) = 1 / (|p|^2 - k0^2 - i eps) (Sec. 2.2,
+ * Eq. of g~; Algorithm 1's table), p = 2 pi m / (N dx) with m the signed
+ * FFT index, in FP64, scaled 1/(N_x N_y), folded to [N_x/2+1][N_y/2+1] and
+ * rounded to the plan dtype.  vv (NULL: none) adds the table g~ VV of the
+ * Case II k-space potential, which tbs_iterate then applies in every
+ * iteration after the first.  eps >= 0 (the paper: 0.8 k^2).
+ * TBS_ERR_STATE on a padded plan.  Asynchronous on the plan's stream. */
+int tbs_green_periodic(tbs_plan *plan, double eps, const tbs_kspace_potential *vv);
+
+/* Coefficients of the Case II potential from the power law alpha0 omega^nu
+ * (Sec. 2.1.2): tau = -2 alpha0 c^(nu-1), eta = 2 alpha0 c^nu tan(pi nu / 2);
+ * out->nu = nu, out->omega = omega.  alpha0 in Np (rad/s)^-nu / m.  Host only.
+ * (nu = 1 makes eta infinite: the paper requires nu != 1.) */
+int tbs_kspace_coefficients(double alpha0, double nu, double c, double omega,
+                            tbs_kspace_potential *out);
+
+/* The paper's sigmoid absorbing layer along one axis (Sec. 3.1 Eq.
+ * ABL_profile): out[i] = 1 / (1 + exp(-zeta (x_i - mu/2))) for cells whose
+ * distance x_i = min(i, n-1-i) dx (in cm) from the nearer outer edge is below
+ * the layer width mu = mu_cells dx, else 1.  zeta in Np/cm.  Host only;
+ * out: host double [n].  The 2D layer is the product of the axis profiles. */
+int tbs_abl_profile(int64_t n, double dx, double zeta, double mu_cells, double *out);
+
+/* The paper's fixed-point iteration (Algorithm 1; Sec. 2.3 Eqs.
+ * TBS_solution_lossless, _absorbing-dispersive, _inhomogeneous):
+ *   psi_0 = G s,  psi_{l+1} = A (G(V psi_l) + psi_0) = A G(V psi_l + s),
+ * G = F^-1 g~ F (g~ VV with a Case II table), A = mask_y[y] mask_x[x] the
+ * absorbing layer (not applied to psi_0), stopping at the first l whose
+ * error sum_x |psi_l - psi_{l-1}| / sum_x |psi_{l-1}| on row check_row
+ * (Sec. 3.1 Eq. Error; the largest over right-hand sides) is below tol.
+ *   source   : dev [B][N_y][N_x] plan dtype
+ *   potential: dev [N_y][N_x] plan dtype, or NULL (V = 1: Case II, where the
+ *              potential is in the spectrum)
+ *   mask_x, mask_y: dev float64 [N_x], [N_y] or NULL (no layer on that axis)
+ *   check_row: 0 <= check_row < N_y (the paper: the array's centre row)
+ *   tol >= 0 (the paper: 1e-5); 1 <= max_iter <= 1e6 (the paper: 2000)
+ *   psi_out  : dev [B][N_y][N_x] plan dtype, the last iterate (must not alias
+ *              source)
+ *   iters_out: host int or NULL: the iteration count l
+ *   err_out  : host double [max_iter] or NULL: errors of iterations 1..l
+ * Synchronises once per 8 iterations.  Returns TBS_OK when the tolerance is
+ * reached, TBS_WARN_NOT_CONVERGED (outputs valid) when max_iter is,
+ * TBS_WARN_NONFINITE on a NaN/Inf error.  TBS_ERR_STATE before
+ * tbs_green_periodic or on a padded plan. */
+int tbs_iterate(tbs_plan *plan, const void *source, const void *potential, const double *mask_x,
+                const double *mask_y, int check_row, double tol, int max_iter, void *psi_out,
+                int *iters_out, double *err_out);
 
 /* Gradient of Re<q, p_L> with respect to V for each right-hand side, i.e. the
  * adjoint of the truncated series:

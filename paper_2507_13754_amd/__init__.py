@@ -23,7 +23,7 @@ LIB_PATH = os.environ.get("TBS_LIBRARY", os.path.join(HERE, "libtbs.so"))
 
 TBS_C64, TBS_C128 = 0, 1
 TBS_OK = 0
-TBS_WARN_NONFINITE, TBS_WARN_DIVERGING = 1, 2
+TBS_WARN_NONFINITE, TBS_WARN_DIVERGING, TBS_WARN_NOT_CONVERGED = 1, 2, 3
 TBS_ADJ_STORE, TBS_ADJ_RECOMPUTE = 0, 1
 
 # Every entry point of include/tbs.h.
@@ -34,7 +34,9 @@ EXPORTS = (
     "tbs_potential", "tbs_solve", "tbs_harmonic_source", "tbs_harmonic_source_n", "tbs_adjoint", "tbs_misfit",
     "tbs_speed_gradient", "tbs_profile_enable", "tbs_profile_read", "tbs_plan_destroy",
     "tbs_last_error", "tbs_batch_create", "tbs_batch_solve", "tbs_batch_destroy",
-    "tbs_batch_last_error", "tbs_plan_autotune",
+    "tbs_batch_last_error", "tbs_plan_autotune", "tbs_green_periodic", "tbs_abl_profile",
+    "tbs_kspace_coefficients",
+    "tbs_iterate",
 )
 PASS_KINDS = ("row_first", "row_mid", "row_last", "col_conv", "col_fwd", "col_inv")
 
@@ -101,6 +103,12 @@ def library() -> ctypes.CDLL:
         "tbs_batch_destroy": (None, [vp]),
         "tbs_batch_last_error": (ctypes.c_char_p, [vp]),
         "tbs_last_error": (ctypes.c_char_p, [vp]),
+        "tbs_green_periodic": (ctypes.c_int, [vp, ctypes.c_double, vp]),
+        "tbs_kspace_coefficients": (ctypes.c_int, [ctypes.c_double] * 4 + [vp]),
+        "tbs_abl_profile": (ctypes.c_int, [ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                                           ctypes.c_double, dp]),
+        "tbs_iterate": (ctypes.c_int, [vp, vp, vp, vp, vp, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                       vp, ctypes.POINTER(ctypes.c_int), dp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -178,6 +186,29 @@ def _ptr(t, dtype, shape: Optional[Sequence[int]] = None, name: str = "tensor"):
     if shape is not None and tuple(t.shape) != tuple(shape):
         raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
     return ctypes.c_void_p(t.data_ptr())
+
+
+class KSpacePotential(ctypes.Structure):
+    """Case II k-space potential VV = eta |p|^(nu+1) - i (tau omega |p|^nu + eps)."""
+    _fields_ = [("tau", ctypes.c_double), ("eta", ctypes.c_double), ("nu", ctypes.c_double),
+                ("omega", ctypes.c_double)]
+
+
+def kspace_potential(alpha0: float, nu: float, c: float, omega: float) -> KSpacePotential:
+    """Case II coefficients (tau, eta) of the power law alpha0 omega^nu at speed c."""
+    out = KSpacePotential()
+    _check(library().tbs_kspace_coefficients(float(alpha0), float(nu), float(c), float(omega),
+                                             ctypes.byref(out)), what="tbs_kspace_coefficients")
+    return out
+
+
+def abl_profile(n: int, dx: float, zeta: float, mu_cells: float) -> np.ndarray:
+    """The sigmoid absorbing-layer profile along one axis (host, float64)."""
+    out = np.empty(int(n), dtype=np.float64)
+    _check(library().tbs_abl_profile(int(n), float(dx), float(zeta), float(mu_cells),
+                                     out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+           what="tbs_abl_profile")
+    return out
 
 
 class Plan:
@@ -333,6 +364,33 @@ class Plan:
         _check(library().tbs_harmonic_source_n(self._h, int(n), ptrs, cp, omega, rho, BA, op), self._h,
                "tbs_harmonic_source_n")
         return out
+
+    # -- the paper's periodic scheme (plans made with padding=1) --
+    def green_periodic(self, eps: float, vv: Optional[KSpacePotential] = None):
+        self._sync_stream()
+        _check(library().tbs_green_periodic(self._h, float(eps), ctypes.byref(vv) if vv is not None else None),
+               self._h, "tbs_green_periodic")
+        return self
+
+    def iterate(self, source, potential=None, mask_x=None, mask_y=None, check_row: Optional[int] = None,
+                tol: float = 1e-5, max_iter: int = 2000, out=None):
+        """Fixed-point iteration of the paper; returns (psi, iterations, errors)."""
+        torch = _torch()
+        sp = _ptr(source, self.dtype, self._bshape(), "source")
+        vp = _ptr(potential, self.dtype, self.shape, "potential")
+        mx = _ptr(mask_x, torch.float64, (self.shape[1],), "mask_x")
+        my = _ptr(mask_y, torch.float64, (self.shape[0],), "mask_y")
+        if out is None:
+            out = torch.empty(self._bshape(), dtype=self.dtype, device=source.device)
+        op = _ptr(out, self.dtype, self._bshape(), "out")
+        errs = np.zeros(int(max_iter), dtype=np.float64)
+        n = ctypes.c_int()
+        row = self.shape[0] // 2 if check_row is None else int(check_row)
+        self._sync_stream()
+        _check(library().tbs_iterate(self._h, sp, vp, mx, my, row, float(tol), int(max_iter), op,
+                                     ctypes.byref(n), errs.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+               self._h, "tbs_iterate")
+        return out, int(n.value), errs[: n.value].copy()
 
     def adjoint(self, source, potential, nterms: int, adj_source, out=None,
                 flags: int = TBS_ADJ_STORE, residual: bool = False):

@@ -58,6 +58,13 @@ struct tbs_plan {
   size_t jpart_cap = 0;
   int64_t device_bytes = 0;
   bool green_ready = false;
+  // periodic (unpadded) plans of the paper's own scheme
+  bool periodic = false;
+  void* ghat_vv = nullptr;  // g~ VV (Case II k-space potential) or NULL
+  void* psi0 = nullptr;     // [B][P] G s of the current iteration
+  int* iflags = nullptr;    // device {done, iterations}
+  double* ierrs = nullptr;  // device error history
+  size_t ierrs_cap = 0;
   std::string err;
   // per-pass event timing
   bool prof = false;
@@ -453,6 +460,8 @@ int forward_series(tbs_plan* p, const void* source, const void* V, int L, void* 
 
 int check_plan_ready(tbs_plan* p) {
   if (!p) return TBS_ERR_INVALID;
+  if (p->periodic)
+    return fail(p, TBS_ERR_STATE, "periodic plans run tbs_iterate only");
   if (!p->green_ready)
     return fail(p, TBS_ERR_STATE, "the Green spectrum is not set: call tbs_green_tabulate first");
   return TBS_OK;
@@ -652,6 +661,7 @@ const char* tbs_status_string(int s) {
     case TBS_ERR_STATE: return "TBS_ERR_STATE";
     case TBS_WARN_NONFINITE: return "TBS_WARN_NONFINITE";
     case TBS_WARN_DIVERGING: return "TBS_WARN_DIVERGING";
+    case TBS_WARN_NOT_CONVERGED: return "TBS_WARN_NOT_CONVERGED";
     default: return "unknown status";
   }
 }
@@ -731,6 +741,12 @@ void tbs_plan_destroy(tbs_plan* p) {
   dev_free(p, p->ckpt, 0);
   q = p->jpart;
   dev_free(p, q, 0);
+  dev_free(p, p->ghat_vv, 0);
+  dev_free(p, p->psi0, 0);
+  q = p->iflags;
+  dev_free(p, q, 0);
+  q = p->ierrs;
+  dev_free(p, q, 0);
   for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
   delete p;
 }
@@ -744,16 +760,27 @@ int tbs_plan_create(tbs_plan** out, int ndim, const int64_t grid[3], double dx, 
   if (!(dx > 0) || !is_fin(dx)) return fail(nullptr, TBS_ERR_INVALID, "dx must be > 0");
   if (!(k0.re > 0) || !(k0.im >= 0) || !is_fin(k0.re) || !is_fin(k0.im))
     return fail(nullptr, TBS_ERR_INVALID, "k0 needs Re k0 > 0 and Im k0 >= 0");
-  if (padding < 2) return fail(nullptr, TBS_ERR_INVALID, "padding must be >= 2");
+  if (padding < 1) return fail(nullptr, TBS_ERR_INVALID, "padding must be >= 1");
   if (dtype != TBS_C64 && dtype != TBS_C128) return fail(nullptr, TBS_ERR_INVALID, "bad dtype");
   if (batch < 1 || batch > 4096) return fail(nullptr, TBS_ERR_INVALID, "batch must be 1..4096");
+  if (padding == 1) {
+    // periodic plan: 2D, both sizes powers of two in [16, 4096]
+    if (ndim != 2) return fail(nullptr, TBS_ERR_UNSUPPORTED, "periodic plans are 2D");
+    for (int d = 0; d < 2; ++d) {
+      const int64_t n = grid[d];
+      if (n < 16 || n > 4096 || (n & (n - 1)) != 0)
+        return fail(nullptr, TBS_ERR_UNSUPPORTED, "periodic grid sizes must be powers of two in [16, 4096]");
+    }
+  }
   tbs_plan* p = new (std::nothrow) tbs_plan();
   if (!p) return fail(nullptr, TBS_ERR_OOM, "host allocation failed");
   p->ndim = ndim;
   p->N[0] = grid[0];
   p->N[1] = grid[1];
   p->N[2] = ndim == 3 ? grid[2] : 1;
-  for (int d = 0; d < ndim; ++d) {
+  p->periodic = padding == 1;
+  for (int d = 0; d < ndim && p->periodic; ++d) p->M[d] = p->N[d];
+  for (int d = 0; d < ndim && !p->periodic; ++d) {
     if (p->N[d] < 1 || p->N[d] > 2048) {
       delete p;
       return fail(nullptr, TBS_ERR_UNSUPPORTED, "grid sizes must be 1..2048");
@@ -784,7 +811,9 @@ int tbs_plan_create(tbs_plan** out, int ndim, const int64_t grid[3], double dx, 
   int rc = dev_alloc(p, &p->X, p->X_bytes);
   p->xcur = p->X;
   if (!rc && ndim == 3) rc = dev_alloc(p, &p->Yb, B * p->M[0] * p->M[1] * p->N[2] * p->esz);
-  if (!rc && !p->fp64) rc = dev_alloc(p, &p->kc, B * p->P * p->esz);
+  if (!rc && !p->fp64 && !p->periodic) rc = dev_alloc(p, &p->kc, B * p->P * p->esz);
+  if (!rc && p->periodic) rc = dev_alloc(p, &p->psi0, B * p->P * p->esz);
+  if (!rc && p->periodic) rc = dev_alloc(p, (void**)&p->iflags, 2 * sizeof(int));
   p->ghat_n = (p->M[0] / 2 + 1) * (p->M[1] / 2 + 1) * (ndim == 3 ? p->M[2] / 2 + 1 : 1);
   if (!rc) rc = dev_alloc(p, &p->ghat, (size_t)p->ghat_n * p->esz);
   for (int d = 0; d < ndim && !rc; ++d) rc = upload_twiddles(p, (int)p->M[d], p->fp64, &p->tw[d]);
@@ -816,6 +845,7 @@ int tbs_plan_set_stream(tbs_plan* p, void* s) {
 
 int tbs_green_tabulate(tbs_plan* p) {
   if (!p) return TBS_ERR_INVALID;
+  if (p->periodic) return fail(p, TBS_ERR_STATE, "periodic plans take tbs_green_periodic");
   const int64_t Mx = p->M[0], My = p->M[1], Mz = p->ndim == 3 ? p->M[2] : 1;
   const int64_t M3[3] = {Mx, My, Mz};
   void* W = nullptr;
@@ -874,6 +904,128 @@ int tbs_green_tabulate(tbs_plan* p) {
   cleanup();
   if (he != hipSuccess) return hip_fail(p, he, "green tabulation");
   p->green_ready = true;
+  return TBS_OK;
+}
+
+int tbs_green_periodic(tbs_plan* p, double eps, const tbs_kspace_potential* vv) {
+  if (!p) return TBS_ERR_INVALID;
+  if (!p->periodic) return fail(p, TBS_ERR_STATE, "not a periodic plan (create it with padding 1)");
+  if (!(eps >= 0) || !is_fin(eps)) return fail(p, TBS_ERR_INVALID, "eps must be finite and >= 0");
+  if (vv && (!is_fin(vv->tau) || !is_fin(vv->eta) || !(vv->nu > 0) || !is_fin(vv->nu) ||
+             !(vv->omega > 0) || !is_fin(vv->omega)))
+    return fail(p, TBS_ERR_INVALID, "bad k-space potential parameters");
+  if (vv && !p->ghat_vv) {
+    int rc = dev_alloc(p, &p->ghat_vv, (size_t)p->ghat_n * p->esz);
+    if (rc) return rc;
+  } else if (!vv && p->ghat_vv) {
+    TBS_HIP(p, hipStreamSynchronize(p->stream));
+    dev_free(p, p->ghat_vv, (size_t)p->ghat_n * p->esz);
+  }
+  const double k2r = p->k0.re * p->k0.re - p->k0.im * p->k0.im;
+  const double k2i = 2.0 * p->k0.re * p->k0.im;
+  TBS_LAUNCH(p, tbs::launch_periodic_green(p->ghat, vv ? p->ghat_vv : nullptr, p->fp64, p->M[0],
+                                           p->M[1], p->dx, k2r, k2i, eps, vv ? vv->tau : 0.0,
+                                           vv ? vv->eta : 0.0, vv ? vv->nu : 1.0,
+                                           vv ? vv->omega : 1.0, p->stream));
+  p->green_ready = true;
+  return TBS_OK;
+}
+
+int tbs_kspace_coefficients(double alpha0, double nu, double c, double omega,
+                            tbs_kspace_potential* out) {
+  if (!out || !(alpha0 >= 0) || !(nu > 0) || !(c > 0) || !(omega > 0) || !is_fin(alpha0) ||
+      !is_fin(nu) || !is_fin(c) || !is_fin(omega))
+    return TBS_ERR_INVALID;
+  out->tau = -2.0 * alpha0 * std::pow(c, nu - 1.0);
+  out->eta = 2.0 * alpha0 * std::pow(c, nu) * std::tan(tbs::kPi * nu / 2.0);
+  out->nu = nu;
+  out->omega = omega;
+  return TBS_OK;
+}
+
+int tbs_abl_profile(int64_t n, double dx, double zeta, double mu_cells, double* out) {
+  if (!out || n < 1 || !(dx > 0) || !(zeta >= 0) || !(mu_cells >= 0) || !is_fin(zeta) ||
+      !is_fin(mu_cells))
+    return TBS_ERR_INVALID;
+  const double mu_cm = mu_cells * dx * 100.0;
+  for (int64_t i = 0; i < n; ++i) {
+    const double d_cm = (double)std::min(i, n - 1 - i) * dx * 100.0;
+    out[i] = d_cm < mu_cm ? 1.0 / (1.0 + std::exp(-zeta * (d_cm - 0.5 * mu_cm))) : 1.0;
+  }
+  return TBS_OK;
+}
+
+int tbs_iterate(tbs_plan* p, const void* source, const void* V, const double* mask_x,
+                const double* mask_y, int check_row, double tol, int max_iter, void* psi_out,
+                int* iters_out, double* err_out) {
+  if (!p) return TBS_ERR_INVALID;
+  if (!p->periodic) return fail(p, TBS_ERR_STATE, "not a periodic plan (create it with padding 1)");
+  if (!p->green_ready) return fail(p, TBS_ERR_STATE, "call tbs_green_periodic first");
+  if (!source || !psi_out) return fail(p, TBS_ERR_INVALID, "NULL argument");
+  if (max_iter < 1 || max_iter > 1000000) return fail(p, TBS_ERR_INVALID, "max_iter must be 1..1e6");
+  if (check_row < 0 || check_row >= p->N[1]) return fail(p, TBS_ERR_INVALID, "check_row out of range");
+  if (!(tol >= 0) || !is_fin(tol)) return fail(p, TBS_ERR_INVALID, "tol must be finite and >= 0");
+  int rc = ensure_doubles(p, &p->partials, &p->partials_cap, (size_t)2 * p->batch);
+  if (!rc) rc = ensure_doubles(p, &p->ierrs, &p->ierrs_cap, (size_t)max_iter);
+  if (rc) return rc;
+  TBS_LAUNCH(p, tbs::launch_zero(p->iflags, (int64_t)(2 * sizeof(int)), p->stream));
+
+  tbs::IterArgs a{};
+  a.X = p->X;
+  a.tw = p->tw[0];
+  a.psi = psi_out;
+  a.psi0 = p->psi0;
+  a.src = source;
+  a.V = V;
+  a.mask_x = mask_x;
+  a.mask_y = mask_y;
+  a.partials = p->partials;
+  a.done = nullptr;
+  a.nx = (int)p->N[0];
+  a.nrows = (int)p->N[1];
+  a.nrhs = p->batch;
+  a.check_row = check_row;
+  a.cb = p->cb;
+
+  int nc = 0;
+  tbs::ColArgs c = make_conv2d_args(p, false, &nc);
+  c.op = tbs::COL_CONV_FULL;
+  c.n_in = c.n_out = (int)p->N[1];
+  const int Mx = (int)p->M[0], My = (int)p->M[1];
+
+  // psi0 = G s (no absorbing layer on the first field)
+  a.mode = tbs::ITER_SOURCE;
+  TBS_LAUNCH(p, tbs::launch_iter_row(p->fp64, Mx, a, p->stream));
+  TBS_LAUNCH(p, tbs::launch_iter_col(p->fp64, My, nc, c, nullptr, p->stream));
+  a.mode = tbs::ITER_FIRST;
+  TBS_LAUNCH(p, tbs::launch_iter_row(p->fp64, Mx, a, p->stream));
+
+  a.mode = tbs::ITER_STEP;
+  a.done = p->iflags;
+  if (p->ghat_vv) c.ghat = p->ghat_vv;
+  int flags[2] = {0, 0};
+  const int chunk = 8;
+  for (int it = 1; it <= max_iter;) {
+    const int end = std::min(max_iter, it + chunk - 1);
+    for (; it <= end; ++it) {
+      TBS_LAUNCH(p, tbs::launch_iter_col(p->fp64, My, nc, c, p->iflags, p->stream));
+      TBS_LAUNCH(p, tbs::launch_iter_row(p->fp64, Mx, a, p->stream));
+      TBS_LAUNCH(p, tbs::launch_iter_finish(p->partials, p->batch, it, tol, p->ierrs, p->iflags,
+                                            p->iflags + 1, p->stream));
+    }
+    TBS_HIP(p, hipMemcpyAsync(flags, p->iflags, sizeof(flags), hipMemcpyDeviceToHost, p->stream));
+    TBS_HIP(p, hipStreamSynchronize(p->stream));
+    if (flags[0]) break;
+  }
+  const int n = flags[1];
+  if (iters_out) *iters_out = n;
+  std::vector<double> errs((size_t)std::max(n, 1), 0.0);
+  if (n > 0)
+    TBS_HIP(p, hipMemcpy(errs.data(), p->ierrs, (size_t)n * sizeof(double), hipMemcpyDeviceToHost));
+  if (err_out && n > 0) std::memcpy(err_out, errs.data(), (size_t)n * sizeof(double));
+  for (int i = 0; i < n; ++i)
+    if (!is_fin(errs[(size_t)i])) return fail(p, TBS_WARN_NONFINITE, "non-finite iteration error");
+  if (!flags[0]) return fail(p, TBS_WARN_NOT_CONVERGED, "tolerance not reached within max_iter");
   return TBS_OK;
 }
 
@@ -1056,6 +1208,7 @@ int tbs_speed_gradient(tbs_plan* p, const void* g, const void* dVdc, double* gra
 
 int tbs_plan_autotune(tbs_plan* p, int* row_nr_out, int* conv_nc_out) {
   if (!p) return TBS_ERR_INVALID;
+  if (p->periodic) return fail(p, TBS_ERR_STATE, "periodic plans are not tuned");
   if (!p->green_ready) return fail(p, TBS_ERR_STATE, "tabulate the spectrum before tuning");
   if (p->ndim == 2) {
     static std::mutex mu;
@@ -1193,7 +1346,7 @@ int tbs_batch_create(tbs_batch** out, tbs_plan* const* plans, int nplans) {
   if (!b) return fail(nullptr, TBS_ERR_OOM, "host allocation failed");
   for (int i = 0; i < nplans; ++i) {
     tbs_plan* p = plans[i];
-    if (!p || p->ndim != 2 || !p->green_ready || p->fp64 != plans[0]->fp64) {
+    if (!p || p->ndim != 2 || p->periodic || !p->green_ready || p->fp64 != plans[0]->fp64) {
       delete b;
       return fail(nullptr, TBS_ERR_INVALID,
                   "batch plans must be 2D, tabulated and of one dtype");

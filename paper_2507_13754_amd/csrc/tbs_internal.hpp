@@ -57,7 +57,33 @@ struct ColArgs {
   int64_t g_sx, g_sm;   // table strides for fold(kx), fold(kmid)
   int xcd_remap;
 };
-enum ColOp { COL_CONV = 0, COL_FWD = 1, COL_INV = 2, COL_FULL = 3 };
+// COL_CONV_FULL: the convolution on unpadded (periodic) lines, every value
+// loaded and stored.
+enum ColOp { COL_CONV = 0, COL_FWD = 1, COL_INV = 2, COL_FULL = 3, COL_CONV_FULL = 4 };
+
+// Row pass of the paper's periodic fixed-point iteration on unpadded 2D grids
+// (lines of M = N values, same intermediate layout as RowArgs).
+enum IterMode {
+  ITER_SOURCE = 0,  // w = s                       -> forward FFT -> X
+  ITER_FIRST = 1,   // psi0 = psi = IFFT(X)        -> w = V psi -> forward FFT -> X
+  ITER_STEP = 2     // psi = mask (IFFT(X) + psi0)  -> w = V psi -> forward FFT -> X
+};
+struct IterArgs {
+  void* X;
+  const void* tw;
+  void* psi;            // [B][ny][nx] current field (read at the check row, then overwritten)
+  void* psi0;           // [B][ny][nx] G s
+  const void* src;      // ITER_SOURCE: [B][ny][nx]
+  const void* V;        // [ny][nx] or NULL (V = 1: the k-space potential lives in the spectrum)
+  const double* mask_x; // [nx] or NULL
+  const double* mask_y; // [ny] or NULL
+  double* partials;     // ITER_STEP: [B][2] = sum |psi_new - psi_old|, sum |psi_old| on the check row
+  const int* done;      // skip the launch when *done != 0 (NULL: never)
+  int nx, nrows, nrhs;
+  int mode;
+  int check_row;
+  int cb;
+};
 
 // FFT lengths with compiled kernels: powers of two, 3 * 2^a and 5 * 2^a.
 #define TBS_LENGTHS_POW2(X) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)
@@ -109,6 +135,15 @@ int launch_row_group(bool fp64, int M, int cb, int nr, const RowArgs* descs, con
                      int ngroups, int total_blocks, hipStream_t s);
 int launch_col_group(bool fp64, int M, int nc, const ColArgs* descs, const int* starts, int ngroups,
                      int total_blocks, hipStream_t s);
+
+// Periodic (unpadded, power-of-two) passes of the paper's fixed-point iteration.
+int launch_iter_row(bool fp64, int M, const IterArgs& a, hipStream_t s);
+int launch_iter_col(bool fp64, int M, int nc, const ColArgs& a, const int* done, hipStream_t s);
+int launch_iter_finish(const double* partials, int nrhs, int iter, double tol, double* errs,
+                       int* done, int* iters, hipStream_t s);
+int launch_periodic_green(void* ghat, void* ghat_vv, bool fp64, int64_t Mx, int64_t My, double dx,
+                          double k2r, double k2i, double eps, double tau, double eta, double nu,
+                          double omega, hipStream_t s);
 
 // Elementwise / reduction kernels.
 int launch_finish_norms(const double* partials, int nterms, int nvalid, int nrhs, int nblk,

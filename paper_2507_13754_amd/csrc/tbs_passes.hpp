@@ -241,6 +241,7 @@ __device__ __forceinline__ void col_pass_body(const ColArgs& a, const int lb) {
   constexpr int LD = lds_len(M);
   constexpr bool HALF_IN = (OP == COL_CONV || OP == COL_FWD);
   constexpr bool HALF_OUT = (OP == COL_CONV || OP == COL_INV);
+  constexpr bool CONV = (OP == COL_CONV || OP == COL_CONV_FULL);
   using LdsT = typename std::conditional<SPLIT, T, cx<T>>::type;
   __shared__ LdsT sh[NC * LD];
 
@@ -275,7 +276,7 @@ __device__ __forceinline__ void col_pass_body(const ColArgs& a, const int lb) {
     v[j] = ld ? in[ib + pos * a.in_astride] : cx<T>{T(0), T(0)};
   }
   if constexpr (OP != COL_INV) fft<T, M, E, false, SPLIT>(v, shc, tw, tt);
-  if constexpr (OP == COL_CONV) {
+  if constexpr (CONV) {
     const cx<T>* g = (const cx<T>*)a.ghat;
     const int kx = blk * a.cb + c0 + (col % a.cb);
     const int64_t gb = fold(kx, a.mx) * a.g_sx + fold(i0, a.mm) * a.g_sm;
@@ -285,7 +286,7 @@ __device__ __forceinline__ void col_pass_body(const ColArgs& a, const int lb) {
       v[j] = a.conj_g ? cmulc(v[j], gv) : cmul(v[j], gv);
     }
   }
-  if constexpr (OP == COL_CONV || OP == COL_INV) fft<T, M, E, true, SPLIT>(v, shc, tw, tt);
+  if constexpr (CONV || OP == COL_INV) fft<T, M, E, true, SPLIT>(v, shc, tw, tt);
   if (cvalid) {
 #pragma unroll
     for (int j = 0; j < E; ++j) {

@@ -87,7 +87,7 @@ def test_plan_create_rejects_bad_arguments():
         (2, g, -1.0, k0, 2, 0, 1),                    # dx
         (2, g, 1e-3, tbs.c128(-1.0, 0.0), 2, 0, 1),   # Re k0 <= 0
         (2, g, 1e-3, tbs.c128(1.0, -1.0), 2, 0, 1),   # Im k0 < 0
-        (2, g, 1e-3, k0, 1, 0, 1),                    # padding
+        (2, g, 1e-3, k0, 0, 0, 1),                    # padding
         (2, g, 1e-3, k0, 2, 7, 1),                    # dtype
         (2, g, 1e-3, k0, 2, 0, 0),                    # batch
     ]
@@ -106,3 +106,21 @@ def test_null_safe_entry_points():
     assert L.tbs_solve(None, None, None, 4, None, None) == -1
     assert L.tbs_green_tabulate(None) == -1
     assert L.tbs_status_string(-3) == b"TBS_ERR_OOM"
+
+
+def test_periodic_plan_rejections():
+    """padding 1 makes a periodic plan: 2D only, power-of-two sizes 16..4096."""
+    L = tbs.library()
+    h = ctypes.c_void_p()
+    k = tbs.c128(100.0, 0.0)
+    for grid, nd in [((64, 64, 8), 3), ((48, 64, 1), 2), ((64, 8, 1), 2), ((8192, 64, 1), 2)]:
+        g = (ctypes.c_int64 * 3)(*grid)
+        assert L.tbs_plan_create(ctypes.byref(h), nd, g, 1e-3, k, 1, 0, 1, None) == -2, grid
+        assert h.value is None
+
+
+@pytest.mark.parametrize("n,dx,mu", [(1200, 20e-6, 450), (300, 1e-4, 40), (17, 1e-3, 0)])
+def test_abl_profile_matches_oracle(n, dx, mu):
+    got = tbs.abl_profile(n, dx, 21.48, mu)
+    ref = oracle.abl_profile(n, dx, 21.48, mu)
+    assert np.allclose(got, ref, rtol=1e-15, atol=0)

@@ -297,3 +297,59 @@ def small_medium(grid: Sequence[int], dx: float, contrast: float, seed: int) -> 
     """Sound speed c0 (1 + contrast * g) with g a smooth unit GRF (correlation
     length 4 cells); for parity tests on small ragged grids."""
     return C0 * (1.0 + contrast * gaussian_random_field(grid, 4.0, seed))
+
+
+# --------------------------------------------------- the paper's own setups --
+
+@dataclasses.dataclass
+class PeriodicCase:
+    """Inputs of the paper's periodic scheme (Sec. 3.1, Algorithm 1)."""
+    name: str
+    n: int
+    dx: float
+    c0: float
+    omega: float
+    eps_factor: float          # eps = eps_factor * (omega / c0)^2
+    c: np.ndarray              # sound speed map [n][n] (scatterer inside)
+    sources: np.ndarray        # [1][n][n] complex grid values of S
+    alpha0: float              # Case II power law (0: no k-space potential)
+    nu: float
+    dispersion: bool           # Case II: keep the dispersion (eta) term
+    zeta: float                # absorbing layer, Np/cm
+    mu_cells: float            # absorbing layer width in cells
+    check_row: int
+    tol: float = 1e-5
+    max_iter: int = 2000
+
+
+def paper_periodic(case: str = "homogeneous", n: int = 4096, vs: float = 1650.0) -> PeriodicCase:
+    """The paper's 2D transducer setup scaled to n cells per side (n = 4096:
+    the paper's grid): dx = 20 um, v_f = 1500 m/s, f = 55 v_f / (4096 dx)
+    = 1007080 Hz, eps = 0.8 k_f^2, a line of 501 (scaled: 501 n / 4096, odd)
+    point sources of value -1e6 i at column 675 (scaled) centred on the
+    middle row, the absorbing layer zeta = 21.48 Np/cm over 450 cells
+    (scaled), the stopping row = the middle row, tol 1e-5, 2000 iterations
+    at most.  case: "homogeneous" (Case I, lossless), "absorbing" (Case II
+    with alpha0 = 5.5e-10, nu = 1.5 and the dispersion term dropped),
+    "absorbing-dispersive" (Case II with both terms), "inhomogeneous"
+    (Case III: a disk of radius 50 cells (scaled) and speed vs at the domain
+    centre)."""
+    if case not in ("homogeneous", "absorbing", "absorbing-dispersive", "inhomogeneous"):
+        raise ValueError(case)
+    dx, c0 = 20e-6, 1500.0
+    f = 55.0 * c0 / (4096 * dx)
+    s = n / 4096.0
+    c = np.full((n, n), c0)
+    if case == "inhomogeneous":
+        r = max(2.0, 50.0 * s)
+        yy, xx = np.mgrid[0:n, 0:n]
+        c[(yy - n // 2) ** 2 + (xx - n // 2) ** 2 <= r * r] = vs
+    src = np.zeros((1, n, n), np.complex128)
+    half = max(1, int(round(250 * s)))
+    col = max(1, int(round(675 * s)) - 1)
+    src[0, n // 2 - half: n // 2 + half + 1, col] = -1e6j
+    a0 = 5.5e-10 if case in ("absorbing", "absorbing-dispersive") else 0.0
+    return PeriodicCase(name=f"paper-{case}-{n}", n=n, dx=dx, c0=c0, omega=2 * math.pi * f,
+                        eps_factor=0.8, c=c, sources=src, alpha0=a0, nu=1.5,
+                        dispersion=case == "absorbing-dispersive", zeta=21.48,
+                        mu_cells=max(2.0, 450.0 * s), check_row=n // 2)
