@@ -30,7 +30,8 @@ What it computes (citations are to the paper's sections and equations):
   spatial potential (Cases I, III, IV) or the k-space potential of the
   absorbing-dispersive medium (Case II, Sec. 2.3.2), the sigmoid absorbing
   layer applied after every iteration but the first (Eq. ABL_profile), and
-  the centre-row relative L1 change as stopping error (Eq. Error);
+  the centre-row relative L1 change as stopping error (Eq. Error), and the
+  convergent Born series the paper names as its extension (gamma = i V / eps);
 * the exact gradient of a receiver misfit of the truncated series with
   respect to the sound speed (the adjoint of the series; not in the paper).
 
@@ -393,6 +394,50 @@ def paper_iterate(gtilde: np.ndarray, s: np.ndarray, V: Optional[np.ndarray] = N
         if err < tol:
             return psi, it, np.array(errs)
     return psi, max_iter, np.array(errs)
+
+
+def cbs_iterate(gtilde: np.ndarray, s: np.ndarray, V: np.ndarray, eps: float,
+                mask: Optional[np.ndarray] = None, check_row: Optional[int] = None,
+                tol: float = 1e-5, max_iter: int = 2000):
+    """The convergent Born series the paper names as its extension (Sec. 1 and
+    Sec. 5; the preconditioned iteration of Osnabrugge et al., which the paper
+    cites): gamma = (i / eps) V, starting from psi_1 = gamma G s, then
+      psi_{l+1} = psi_l + gamma (G(V psi_l + s) - psi_l)   [* ABL],
+    with G = F^-1 g~ F and V = k^2 - k0^2 - i eps; it converges for
+    eps >= max |k^2 - k0^2| (the condition the paper quotes).  Same stopping
+    error and return values as paper_iterate (iterations count the updates
+    after psi_1)."""
+    gamma = 1j * V / eps
+    S = np.fft.fft2(s)
+    psi = gamma * np.fft.ifft2(gtilde * S)
+    c = s.shape[0] // 2 if check_row is None else check_row
+    errs = []
+    for it in range(1, max_iter + 1):
+        new = psi + gamma * (np.fft.ifft2(gtilde * np.fft.fft2(V * psi + s)) - psi)
+        if mask is not None:
+            new = new * mask
+        err = float(np.sum(np.abs(new[c] - psi[c])) / np.sum(np.abs(psi[c])))
+        errs.append(err)
+        psi = new
+        if err < tol:
+            return psi, it, np.array(errs)
+    return psi, max_iter, np.array(errs)
+
+
+def periodic_helmholtz_dense(k2: np.ndarray, dx: float, s: np.ndarray) -> np.ndarray:
+    """Direct solve of -lap psi - k(x)^2 psi = s on the periodic grid with the
+    spectral Laplacian (|p|^2 in k-space): the equation the periodic
+    iterations converge to (Sec. 2.2 Eq. acoustic_waveequn5 with U = k^2 - k_f^2).
+    Dense, for grids of a few hundred points."""
+    ny, nx = s.shape
+    n = nx * ny
+    px = 2.0 * np.pi * np.fft.fftfreq(nx, d=dx)
+    py = 2.0 * np.pi * np.fft.fftfreq(ny, d=dx)
+    P2 = (py[:, None] ** 2 + px[None, :] ** 2).ravel()
+    eye = np.eye(n).reshape(n, ny, nx)
+    lap = np.fft.ifft2(np.fft.fft2(eye) * P2.reshape(ny, nx)[None]).reshape(n, n).T
+    A = lap - np.diag(np.asarray(k2).ravel())
+    return np.linalg.solve(A, s.ravel()).reshape(ny, nx)
 
 
 # ---------------------------------------------------------------- adjoint ---

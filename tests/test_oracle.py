@@ -429,6 +429,60 @@ def test_abl_profile_shape():
     assert m[225, 225] == pytest.approx(0.25)
 
 
+def _strong_scatterer(n=16, seed=9, contrast=0.6):
+    dx = 1.0
+    k0 = 2 * np.pi / 6.0
+    blob = np.exp(-(((np.arange(n) - n / 2)[:, None] ** 2 + (np.arange(n) - n / 2)[None, :] ** 2) / 8.0))
+    k = k0 * (1 + contrast * blob) + 0.02j * k0
+    k2 = k * k
+    s = np.zeros((n, n), np.complex128)
+    s[3, 5] = 1.0
+    s[n - 4, 2] = 0.5j
+    return dx, k0, k2, s
+
+
+def test_periodic_dense_solve_is_the_helmholtz_solution():
+    """The dense periodic solve satisfies the equation through an independent
+    route (the spectral Laplacian applied by FFTs to the solution)."""
+    dx, k0, k2, s = _strong_scatterer()
+    psi = oracle.periodic_helmholtz_dense(k2, dx, s)
+    px = 2 * np.pi * np.fft.fftfreq(s.shape[1], d=dx)
+    py = 2 * np.pi * np.fft.fftfreq(s.shape[0], d=dx)
+    lap_psi = -np.fft.ifft2(np.fft.fft2(psi) * (py[:, None] ** 2 + px[None, :] ** 2))
+    assert rel(-lap_psi - k2 * psi, s) < 1e-12
+
+
+def test_cbs_converges_where_tbs_diverges():
+    """Strong scatterer (60 % speed contrast): the paper's series diverges
+    (spectral radius of G V above 1), the convergent Born series with
+    eps = max |k^2 - k0^2| reaches the dense periodic Helmholtz solution."""
+    dx, k0, k2, s = _strong_scatterer()
+    dV = k2 - k0 * k0
+    eps = 1.01 * np.max(np.abs(dV))
+    g = oracle.periodic_green_spectrum(k0, eps, dx, s.shape)
+    V = dV - 1j * eps
+    exact = oracle.periodic_helmholtz_dense(k2, dx, s)
+    # TBS (paper iteration) on the same potential: the change grows
+    _, _, e_tbs = oracle.paper_iterate(g, s, V=V, tol=0.0, max_iter=60)
+    assert e_tbs[-1] > e_tbs[20]
+    psi, it, errs = oracle.cbs_iterate(g, s, V, eps, tol=1e-12, max_iter=20000)
+    assert it < 20000
+    assert rel(psi, exact) < 1e-9
+
+
+def test_cbs_weak_scatterer_agrees_with_tbs_limit():
+    """Weak medium: CBS and the paper's iteration converge to the same field."""
+    dx, k0, k2, s = _strong_scatterer(contrast=0.02)
+    dV = k2 - k0 * k0
+    eps = 0.8 * k0 * k0
+    g = oracle.periodic_green_spectrum(k0, eps, dx, s.shape)
+    V = dV - 1j * eps
+    a, _, _ = oracle.paper_iterate(g, s, V=V, tol=1e-13, max_iter=20000)
+    b, _, _ = oracle.cbs_iterate(g, s, V, eps, tol=1e-13, max_iter=20000)
+    assert rel(a, b) < 1e-9
+    assert rel(b, oracle.periodic_helmholtz_dense(k2, dx, s)) < 1e-9
+
+
 # ---------------------------------------------------------------- adjoint ---
 
 def test_adjoint_green_operator_dot_product():
