@@ -67,6 +67,11 @@ typedef struct {
   double tau, eta, nu, omega;
 } tbs_kspace_potential;
 
+enum tbs_iterate_flags {
+  TBS_ITER_PAPER = 0, /* the paper's fixed-point iteration (Algorithm 1) */
+  TBS_ITER_CBS = 1    /* the convergent Born series the paper names as its extension */
+};
+
 enum tbs_adjoint_flags {
   TBS_ADJ_STORE = 0,     /* keep all L-1 forward partial sums in HBM */
   TBS_ADJ_RECOMPUTE = 1  /* keep ~sqrt(L) checkpoints and recompute segments */
@@ -241,13 +246,20 @@ int tbs_abl_profile(int64_t n, double dx, double zeta, double mu_cells, double *
  *              source)
  *   iters_out: host int or NULL: the iteration count l
  *   err_out  : host double [max_iter] or NULL: errors of iterations 1..l
+ *   flags    : TBS_ITER_PAPER, or TBS_ITER_CBS for the convergent Born
+ *              series (Osnabrugge et al., cited by the paper as its extension
+ *              to strong scatterers): gamma = i V / eps (eps of
+ *              tbs_green_periodic), psi_1 = gamma G s,
+ *              psi_{l+1} = A (psi_l + gamma (G(V psi_l + s) - psi_l)),
+ *              convergent for eps >= max |k^2 - k0^2|; needs the potential
+ *              (V = k^2 - k0^2 - i eps) and no Case II table.
  * Synchronises once per 8 iterations.  Returns TBS_OK when the tolerance is
  * reached, TBS_WARN_NOT_CONVERGED (outputs valid) when max_iter is,
  * TBS_WARN_NONFINITE on a NaN/Inf error.  TBS_ERR_STATE before
  * tbs_green_periodic or on a padded plan. */
 int tbs_iterate(tbs_plan *plan, const void *source, const void *potential, const double *mask_x,
                 const double *mask_y, int check_row, double tol, int max_iter, void *psi_out,
-                int *iters_out, double *err_out);
+                int *iters_out, double *err_out, int flags);
 
 /* Gradient of Re<q, p_L> with respect to V for each right-hand side, i.e. the
  * adjoint of the truncated series:

@@ -25,6 +25,7 @@ TBS_C64, TBS_C128 = 0, 1
 TBS_OK = 0
 TBS_WARN_NONFINITE, TBS_WARN_DIVERGING, TBS_WARN_NOT_CONVERGED = 1, 2, 3
 TBS_ADJ_STORE, TBS_ADJ_RECOMPUTE = 0, 1
+TBS_ITER_PAPER, TBS_ITER_CBS = 0, 1
 
 # Every entry point of include/tbs.h.
 EXPORTS = (
@@ -108,7 +109,7 @@ def library() -> ctypes.CDLL:
         "tbs_abl_profile": (ctypes.c_int, [ctypes.c_int64, ctypes.c_double, ctypes.c_double,
                                            ctypes.c_double, dp]),
         "tbs_iterate": (ctypes.c_int, [vp, vp, vp, vp, vp, ctypes.c_int, ctypes.c_double, ctypes.c_int,
-                                       vp, ctypes.POINTER(ctypes.c_int), dp]),
+                                       vp, ctypes.POINTER(ctypes.c_int), dp, ctypes.c_int]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -373,8 +374,9 @@ class Plan:
         return self
 
     def iterate(self, source, potential=None, mask_x=None, mask_y=None, check_row: Optional[int] = None,
-                tol: float = 1e-5, max_iter: int = 2000, out=None):
-        """Fixed-point iteration of the paper; returns (psi, iterations, errors)."""
+                tol: float = 1e-5, max_iter: int = 2000, out=None, cbs: bool = False):
+        """Fixed-point iteration of the paper (cbs=True: the convergent Born
+        series); returns (psi, iterations, errors)."""
         torch = _torch()
         sp = _ptr(source, self.dtype, self._bshape(), "source")
         vp = _ptr(potential, self.dtype, self.shape, "potential")
@@ -388,7 +390,8 @@ class Plan:
         row = self.shape[0] // 2 if check_row is None else int(check_row)
         self._sync_stream()
         _check(library().tbs_iterate(self._h, sp, vp, mx, my, row, float(tol), int(max_iter), op,
-                                     ctypes.byref(n), errs.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+                                     ctypes.byref(n), errs.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     TBS_ITER_CBS if cbs else TBS_ITER_PAPER),
                self._h, "tbs_iterate")
         return out, int(n.value), errs[: n.value].copy()
 

@@ -61,6 +61,7 @@ struct tbs_plan {
   // periodic (unpadded) plans of the paper's own scheme
   bool periodic = false;
   void* ghat_vv = nullptr;  // g~ VV (Case II k-space potential) or NULL
+  double eps = 0.0;         // the shift of the periodic spectrum
   void* psi0 = nullptr;     // [B][P] G s of the current iteration
   int* iflags = nullptr;    // device {done, iterations}
   double* ierrs = nullptr;  // device error history
@@ -927,6 +928,7 @@ int tbs_green_periodic(tbs_plan* p, double eps, const tbs_kspace_potential* vv) 
                                            p->M[1], p->dx, k2r, k2i, eps, vv ? vv->tau : 0.0,
                                            vv ? vv->eta : 0.0, vv ? vv->nu : 1.0,
                                            vv ? vv->omega : 1.0, p->stream));
+  p->eps = eps;
   p->green_ready = true;
   return TBS_OK;
 }
@@ -957,7 +959,7 @@ int tbs_abl_profile(int64_t n, double dx, double zeta, double mu_cells, double* 
 
 int tbs_iterate(tbs_plan* p, const void* source, const void* V, const double* mask_x,
                 const double* mask_y, int check_row, double tol, int max_iter, void* psi_out,
-                int* iters_out, double* err_out) {
+                int* iters_out, double* err_out, int flags) {
   if (!p) return TBS_ERR_INVALID;
   if (!p->periodic) return fail(p, TBS_ERR_STATE, "not a periodic plan (create it with padding 1)");
   if (!p->green_ready) return fail(p, TBS_ERR_STATE, "call tbs_green_periodic first");
@@ -965,6 +967,10 @@ int tbs_iterate(tbs_plan* p, const void* source, const void* V, const double* ma
   if (max_iter < 1 || max_iter > 1000000) return fail(p, TBS_ERR_INVALID, "max_iter must be 1..1e6");
   if (check_row < 0 || check_row >= p->N[1]) return fail(p, TBS_ERR_INVALID, "check_row out of range");
   if (!(tol >= 0) || !is_fin(tol)) return fail(p, TBS_ERR_INVALID, "tol must be finite and >= 0");
+  if (flags != TBS_ITER_PAPER && flags != TBS_ITER_CBS) return fail(p, TBS_ERR_INVALID, "bad flags");
+  if (flags == TBS_ITER_CBS && (!V || !(p->eps > 0) || p->ghat_vv))
+    return fail(p, TBS_ERR_INVALID, "the convergent series needs a potential, eps > 0 and no k-space table");
+  if (psi_out == source || psi_out == V) return fail(p, TBS_ERR_INVALID, "psi_out aliases an input");
   int rc = ensure_doubles(p, &p->partials, &p->partials_cap, (size_t)2 * p->batch);
   if (!rc) rc = ensure_doubles(p, &p->ierrs, &p->ierrs_cap, (size_t)max_iter);
   if (rc) return rc;
@@ -986,6 +992,8 @@ int tbs_iterate(tbs_plan* p, const void* source, const void* V, const double* ma
   a.nrhs = p->batch;
   a.check_row = check_row;
   a.cb = p->cb;
+  a.cbs = flags == TBS_ITER_CBS ? 1 : 0;
+  a.inv_eps = p->eps > 0 ? 1.0 / p->eps : 0.0;
 
   int nc = 0;
   tbs::ColArgs c = make_conv2d_args(p, false, &nc);
@@ -1003,7 +1011,7 @@ int tbs_iterate(tbs_plan* p, const void* source, const void* V, const double* ma
   a.mode = tbs::ITER_STEP;
   a.done = p->iflags;
   if (p->ghat_vv) c.ghat = p->ghat_vv;
-  int flags[2] = {0, 0};
+  int dflags[2] = {0, 0};
   const int chunk = 8;
   for (int it = 1; it <= max_iter;) {
     const int end = std::min(max_iter, it + chunk - 1);
@@ -1013,11 +1021,11 @@ int tbs_iterate(tbs_plan* p, const void* source, const void* V, const double* ma
       TBS_LAUNCH(p, tbs::launch_iter_finish(p->partials, p->batch, it, tol, p->ierrs, p->iflags,
                                             p->iflags + 1, p->stream));
     }
-    TBS_HIP(p, hipMemcpyAsync(flags, p->iflags, sizeof(flags), hipMemcpyDeviceToHost, p->stream));
+    TBS_HIP(p, hipMemcpyAsync(dflags, p->iflags, sizeof(dflags), hipMemcpyDeviceToHost, p->stream));
     TBS_HIP(p, hipStreamSynchronize(p->stream));
-    if (flags[0]) break;
+    if (dflags[0]) break;
   }
-  const int n = flags[1];
+  const int n = dflags[1];
   if (iters_out) *iters_out = n;
   std::vector<double> errs((size_t)std::max(n, 1), 0.0);
   if (n > 0)
@@ -1025,7 +1033,7 @@ int tbs_iterate(tbs_plan* p, const void* source, const void* V, const double* ma
   if (err_out && n > 0) std::memcpy(err_out, errs.data(), (size_t)n * sizeof(double));
   for (int i = 0; i < n; ++i)
     if (!is_fin(errs[(size_t)i])) return fail(p, TBS_WARN_NONFINITE, "non-finite iteration error");
-  if (!flags[0]) return fail(p, TBS_WARN_NOT_CONVERGED, "tolerance not reached within max_iter");
+  if (!dflags[0]) return fail(p, TBS_WARN_NOT_CONVERGED, "tolerance not reached within max_iter");
   return TBS_OK;
 }
 

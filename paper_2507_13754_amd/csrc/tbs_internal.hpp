@@ -65,8 +65,9 @@ enum ColOp { COL_CONV = 0, COL_FWD = 1, COL_INV = 2, COL_FULL = 3, COL_CONV_FULL
 // (lines of M = N values, same intermediate layout as RowArgs).
 enum IterMode {
   ITER_SOURCE = 0,  // w = s                       -> forward FFT -> X
-  ITER_FIRST = 1,   // psi0 = psi = IFFT(X)        -> w = V psi -> forward FFT -> X
-  ITER_STEP = 2     // psi = mask (IFFT(X) + psi0)  -> w = V psi -> forward FFT -> X
+  ITER_FIRST = 1,   // psi0 = IFFT(X); psi = psi0 (CBS: gamma psi0) -> w = V psi -> FFT -> X
+  ITER_STEP = 2     // psi = mask (IFFT(X) + psi0) (CBS: mask (psi + gamma (IFFT(X) + psi0 - psi)))
+                    //   -> w = V psi -> forward FFT -> X
 };
 struct IterArgs {
   void* X;
@@ -83,6 +84,8 @@ struct IterArgs {
   int mode;
   int check_row;
   int cb;
+  int cbs;              // convergent Born series update (gamma = i V / eps), else the paper's
+  double inv_eps;       // 1 / eps for gamma
 };
 
 // FFT lengths with compiled kernels: powers of two, 3 * 2^a and 5 * 2^a.

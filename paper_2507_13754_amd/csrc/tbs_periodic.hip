@@ -5,6 +5,9 @@
 // which by linearity equals the paper's ABL * ifft(g~ fft(V psi_l + S)) (and,
 // with the k-space potential folded into the spectrum, its Case II form), and
 // the centre-row relative L1 change as stopping error (Sec. 3.1 Eq. Error).
+// The same passes run the convergent Born series the paper names as its
+// extension: psi_1 = gamma psi0, psi_{l+1} = psi_l + gamma (G(V psi_l) + psi0
+// - psi_l), gamma = i V / eps, computed from V in the row pass.
 //
 // Per iteration: one column pass (COL_CONV_FULL) and one row pass (k_iter_row)
 // over the intermediate X[B][M/cb][rows][cb] of the padded solver, then a
@@ -78,16 +81,25 @@ __global__ void __launch_bounds__(NR * (M / E)) TBS_OCCUPANCY(T, M, E, NR, SPLIT
       if (valid && x < a.nx) {
         const int64_t i = sp_base + x;
         cx<T> f = v[j];
+        cx<T> gam = {T(0), T(0)};
+        if (a.cbs) {
+          // gamma = i V / eps
+          const cx<T> vv = Vp[srow + x];
+          gam = cx<T>{(T)(-(double)vv.y * a.inv_eps), (T)((double)vv.x * a.inv_eps)};
+        }
         if (a.mode == ITER_FIRST) {
           psi0[i] = f;
+          if (a.cbs) f = cmul(gam, f);
         } else {
+          const bool need_old = a.cbs || (check_blk && row == a.check_row);
+          const cx<T> o = need_old ? psi[i] : cx<T>{T(0), T(0)};
           f = f + psi0[i];
+          if (a.cbs) f = o + cmul(gam, f - o);
           if (a.mask_x != nullptr || a.mask_y != nullptr) {
             const T m = (T)(my * (a.mask_x != nullptr ? a.mask_x[x] : 1.0));
             f = cscale(f, m);
           }
           if (check_blk && row == a.check_row) {
-            const cx<T> o = psi[i];
             const double dr = (double)f.x - (double)o.x, di = (double)f.y - (double)o.y;
             sd += sqrt(dr * dr + di * di);
             so += sqrt((double)o.x * (double)o.x + (double)o.y * (double)o.y);

@@ -145,3 +145,59 @@ def test_paper_homogeneous_4096(dev):
     _, it, e = gpu_run(dev, c, "c64", c.tol, c.max_iter)
     assert 120 <= it <= 160, it
     assert e[-1] < c.tol <= e[-2]
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_cbs_fixed_iterations_match_oracle(dev, dt):
+    """Convergent Born series on the paper's inhomogeneous setup (vs = 1800,
+    eps = 0.8 k^2 >= max |k^2 - k0^2|), with the absorbing layer: ten updates."""
+    import paper_2507_13754_amd as tbs
+    c = workloads.paper_periodic("inhomogeneous", 128, vs=1800.0)
+    n = c.n
+    k = c.omega / c.c0
+    eps = c.eps_factor * k * k
+    g = oracle.periodic_green_spectrum(k, eps, c.dx, (n, n))
+    V = oracle.potential(c.c, c.omega, c.c0, 0.0, 1.0, eps)
+    mask = oracle.abl_mask((n, n), c.dx, c.zeta, c.mu_cells)
+    p_ref, _, e_ref = oracle.cbs_iterate(g, c.sources[0], V, eps, mask=mask, check_row=c.check_row,
+                                         tol=0.0, max_iter=10)
+    plan = tbs.Plan((n, n), c.dx, k, padding=1, dtype=tdt(dt)).green_periodic(eps)
+    Vd = plan.potential(torch.from_numpy(c.c).to(dev), c.omega, c.c0, 0.0, 1.0, eps)
+    prof = torch.from_numpy(tbs.abl_profile(n, c.dx, c.zeta, c.mu_cells)).to(dev)
+    psi, it, e = plan.iterate(torch.from_numpy(c.sources).to(dev, tdt(dt)), Vd, prof, prof, c.check_row,
+                              0.0, 10, cbs=True)
+    assert it == 10
+    assert rel(psi.cpu().numpy()[0], p_ref) <= TOL[dt] * (3 if dt == "c64" else 1)
+    assert np.allclose(e, e_ref, rtol=1e-9 if dt == "c128" else 2e-3, atol=0)
+    plan.close()
+
+
+def test_cbs_strong_scatterer_reaches_dense_solution(dev):
+    """60 % speed contrast, where the paper's series diverges: the GPU's
+    convergent Born series (FP64, no layer) reaches the dense periodic
+    Helmholtz solution; the paper's iteration on the same input grows."""
+    import paper_2507_13754_amd as tbs
+    n = 16
+    dx = 1.0
+    k0 = 2 * np.pi / 6.0
+    yy, xx = np.mgrid[0:n, 0:n]
+    blob = np.exp(-(((yy - n / 2) ** 2 + (xx - n / 2) ** 2) / 8.0))
+    k = k0 * (1 + 0.6 * blob) + 0.02j * k0
+    k2 = k * k
+    s = np.zeros((1, n, n), np.complex128)
+    s[0, 3, 5] = 1.0
+    s[0, n - 4, 2] = 0.5j
+    eps = 1.01 * np.max(np.abs(k2 - k0 * k0))
+    V = torch.from_numpy(k2 - k0 * k0 - 1j * eps).to(dev)
+    exact = oracle.periodic_helmholtz_dense(k2, dx, s[0])
+    plan = tbs.Plan((n, n), dx, k0, padding=1, dtype=torch.complex128).green_periodic(eps)
+    sd = torch.from_numpy(s).to(dev)
+    psi, it, e = plan.iterate(sd, V, None, None, n // 2, 1e-12, 20000, cbs=True)
+    assert it < 20000
+    assert rel(psi.cpu().numpy()[0], exact) < 1e-9
+    import warnings
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore")
+        _, _, e_tbs = plan.iterate(sd, V, None, None, n // 2, 0.0, 60)
+    assert e_tbs[-1] > e_tbs[20]
+    plan.close()
