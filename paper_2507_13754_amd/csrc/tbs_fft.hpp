@@ -282,9 +282,13 @@ __host__ __device__ constexpr bool stage_is_local(int M, int E, int S) {
   return S + 1 < make_stages(M, E).n && stage_L(M, E, S) % (M / E) == 0;
 }
 
-// LDS index with one pad slot per 16 elements (breaks power-of-two strides).
-__device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
-__host__ __device__ constexpr int lds_len(int M) { return M + M / 16 + 4; }
+// LDS index with one pad slot per 2^TBS_LDS_PAD_SHIFT elements (breaks
+// power-of-two strides).
+#ifndef TBS_LDS_PAD_SHIFT
+#define TBS_LDS_PAD_SHIFT 4
+#endif
+__device__ __forceinline__ int lpad(int i) { return i + (i >> TBS_LDS_PAD_SHIFT); }
+__host__ __device__ constexpr int lds_len(int M) { return M + (M >> TBS_LDS_PAD_SHIFT) + 4; }
 
 // One Stockham stage S and the exchange to stage S+1 (recursively).
 // SPLIT: exchange real and imaginary parts in two rounds through a scalar LDS

@@ -201,3 +201,52 @@ def test_cbs_strong_scatterer_reaches_dense_solution(dev):
         _, _, e_tbs = plan.iterate(sd, V, None, None, n // 2, 0.0, 60)
     assert e_tbs[-1] > e_tbs[20]
     plan.close()
+
+
+def test_periodic_plan_state_errors(dev):
+    """Calls out of order or on the wrong kind of plan fail cleanly."""
+    import paper_2507_13754_amd as tbs
+    n = 32
+    plan = tbs.Plan((n, n), 1e-4, 2000.0, padding=1, dtype=torch.complex64)
+    src = torch.zeros((1, n, n), dtype=torch.complex64, device=dev)
+    with pytest.raises(tbs.TBSError) as e:
+        plan.iterate(src)
+    assert e.value.status == -5                      # before tbs_green_periodic
+    plan.green_periodic(0.8 * 2000.0 ** 2)
+    with pytest.raises(tbs.TBSError) as e:
+        plan.solve(src, None, 3)
+    assert e.value.status == -5                      # the padded series on a periodic plan
+    with pytest.raises(tbs.TBSError) as e:
+        plan.tabulate()
+    assert e.value.status == -5
+    with pytest.raises(tbs.TBSError) as e:
+        plan.iterate(src, None, cbs=True)            # CBS needs the potential
+    assert e.value.status == -1
+    with pytest.raises(tbs.TBSError) as e:
+        plan.iterate(src, check_row=n)               # row out of range
+    assert e.value.status == -1
+    padded = tbs.Plan((n, n), 1e-4, 2000.0, dtype=torch.complex64)
+    with pytest.raises(tbs.TBSError) as e:
+        padded.green_periodic(1.0)
+    assert e.value.status == -5
+    padded.close()
+    plan.close()
+
+
+def test_iterate_reports_not_converged(dev):
+    """max_iter reached above the tolerance: a TBS_WARN_NOT_CONVERGED warning,
+    valid outputs and all max_iter errors."""
+    import warnings
+    import paper_2507_13754_amd as tbs
+    c = workloads.paper_periodic("homogeneous", 64)
+    k = c.omega / c.c0
+    eps = 0.8 * k * k
+    plan = tbs.Plan((64, 64), c.dx, k, padding=1, dtype=torch.complex128).green_periodic(eps)
+    V = plan.potential(torch.from_numpy(c.c).to(dev), c.omega, c.c0, 0.0, 1.0, eps)
+    with warnings.catch_warnings(record=True) as w:
+        warnings.simplefilter("always")
+        psi, it, e = plan.iterate(torch.from_numpy(c.sources).to(dev), V, None, None, c.check_row, 1e-30, 5)
+    assert any(issubclass(x.category, tbs.TBSWarning) and "NOT_CONVERGED" in str(x.message) for x in w)
+    assert it == 5 and len(e) == 5 and np.all(np.isfinite(e))
+    assert torch.isfinite(psi.abs()).all()
+    plan.close()
