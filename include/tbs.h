@@ -296,7 +296,10 @@ typedef struct tbs_batch tbs_batch;
  * grid, k0 and B right-hand sides) for joint solves.  All plans must be 2D,
  * share the dtype and be tabulated; the batch queues its work on the first
  * plan's stream.  The plans must outlive the batch.  Passes of grids whose
- * padded lengths coincide run in one grouped kernel launch per term. */
+ * padded lengths coincide run in one grouped kernel launch per term.  With two
+ * or more plans the work is split in two halves of equal size whose pass
+ * sequences run on two streams, one pass apart (environment variable
+ * TBS_BATCH_CHAINS=1 keeps a single sequence); results are bitwise the same. */
 int tbs_batch_create(tbs_batch **out, tbs_plan *const *plans, int nplans);
 
 /* The L-term series of every plan in the batch (the tbs_solve contract per

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <map>
 #include <mutex>
 #include <cstdio>
@@ -19,6 +20,10 @@
 #include "tbs_internal.hpp"
 
 using tbs::zd;
+
+#ifndef TBS_BATCH_CHAINS_DEFAULT
+#define TBS_BATCH_CHAINS_DEFAULT 2
+#endif
 
 struct tbs_plan {
   int ndim = 2;
@@ -477,7 +482,15 @@ struct tbs_batch {
   hipStream_t stream = nullptr;   // the batch's own stream (graphs are recorded and run here)
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   bool fp64 = false;
+  // Two chains: the plans split in two halves of equal work whose pass
+  // sequences run on two streams, the second one pass behind the first, so
+  // that one chain's memory-bound row pass can share the CUs with the other's
+  // ALU-bound column pass.
+  int chains = 1;
+  hipStream_t stream2 = nullptr;
+  hipEvent_t ev_lag = nullptr, ev_join = nullptr;
   struct Group {
+    int chain = 0;
     int M = 0, cb = 4, nc = 0, nr = 0;
     std::vector<int> members;  // plan indices
     int first = 0;             // index of the first member in the descriptor order
@@ -486,6 +499,7 @@ struct tbs_batch {
   };
   std::vector<Group> rgroups, cgroups;
   std::vector<int> rpos, cpos;   // plan -> position in the row / column descriptor order
+  std::vector<int> chain_of;     // plan -> chain
   // device tables
   void* d_row = nullptr;         // RowArgs [L+1][nplans]
   size_t d_row_bytes = 0;
@@ -521,29 +535,61 @@ void batch_drop_graph(tbs_batch* b) {
   b->key_L = 0;
 }
 
-// Enqueue the whole batched series (no synchronisation).
+// Enqueue the whole batched series (no synchronisation).  With two chains the
+// second runs on stream2, forked from the batch stream after the first
+// chain's first row pass and joined back at the end.
 int batch_enqueue(tbs_batch* b, int L) {
   const int np = (int)b->plans.size();
   const tbs::RowArgs* drow = (const tbs::RowArgs*)b->d_row;
   const tbs::ColArgs* dcol = (const tbs::ColArgs*)b->d_col;
   const int* dst = (const int*)b->d_starts;
-  for (int n = 0; n <= L; ++n) {
+  auto rows = [&](int chain, int n, hipStream_t s) -> int {
     for (const auto& g : b->rgroups) {
+      if (g.chain != chain) continue;
       int e = tbs::launch_row_group(b->fp64, g.M, g.cb, g.nr, drow + (size_t)n * np + g.first,
-                                    dst + g.starts_off, (int)g.members.size(), g.total, b->stream);
+                                    dst + g.starts_off, (int)g.members.size(), g.total, s);
       if (e) return bfail(b, TBS_ERR_HIP, std::string("grouped row pass: ") + hipGetErrorString((hipError_t)e));
     }
-    if (n == L) break;
+    return TBS_OK;
+  };
+  auto cols = [&](int chain, hipStream_t s) -> int {
     for (const auto& g : b->cgroups) {
+      if (g.chain != chain) continue;
       int e = tbs::launch_col_group(b->fp64, g.M, g.nc, dcol + g.first, dst + g.starts_off,
-                                    (int)g.members.size(), g.total, b->stream);
+                                    (int)g.members.size(), g.total, s);
       if (e) return bfail(b, TBS_ERR_HIP, std::string("grouped column pass: ") + hipGetErrorString((hipError_t)e));
     }
+    return TBS_OK;
+  };
+  auto series = [&](int chain, hipStream_t s, hipEvent_t after_first) -> int {
+    for (int n = 0; n <= L; ++n) {
+      int rc = rows(chain, n, s);
+      if (rc) return rc;
+      if (n == 0 && after_first && hipEventRecord(after_first, s) != hipSuccess)
+        return bfail(b, TBS_ERR_HIP, "batch chain event");
+      if (n == L) break;
+      rc = cols(chain, s);
+      if (rc) return rc;
+    }
+    return TBS_OK;
+  };
+  const bool two = b->chains == 2;
+  int rc = series(0, b->stream, two ? b->ev_lag : nullptr);
+  if (!rc && two) {
+    if (hipStreamWaitEvent(b->stream2, b->ev_lag, 0) != hipSuccess)
+      return bfail(b, TBS_ERR_HIP, "batch chain fork");
+    rc = series(1, b->stream2, nullptr);
   }
-  for (tbs_plan* p : b->plans) {
-    int e = tbs::launch_finish_norms(p->partials, L, L, p->batch, row_blocks(p), p->resid, b->stream);
+  if (rc) return rc;
+  for (size_t i = 0; i < b->plans.size(); ++i) {
+    tbs_plan* p = b->plans[i];
+    int e = tbs::launch_finish_norms(p->partials, L, L, p->batch, row_blocks(p), p->resid,
+                                     two && b->chain_of[i] == 1 ? b->stream2 : b->stream);
     if (e) return bfail(b, TBS_ERR_HIP, std::string("norms: ") + hipGetErrorString((hipError_t)e));
   }
+  if (two && (hipEventRecord(b->ev_join, b->stream2) != hipSuccess ||
+              hipStreamWaitEvent(b->stream, b->ev_join, 0) != hipSuccess))
+    return bfail(b, TBS_ERR_HIP, "batch chain join");
   return TBS_OK;
 }
 
@@ -1372,13 +1418,40 @@ int tbs_batch_create(tbs_batch** out, tbs_plan* const* plans, int nplans) {
     tbs_batch_destroy(b);
     return fail(nullptr, TBS_ERR_HIP, "batch stream/events");
   }
+  // two chains for batches of several plans (TBS_BATCH_CHAINS=1 keeps one)
+  b->chains = nplans >= 2 ? TBS_BATCH_CHAINS_DEFAULT : 1;
+  if (const char* env = std::getenv("TBS_BATCH_CHAINS")) b->chains = (std::atoi(env) == 2 && nplans >= 2) ? 2 : 1;
+  if (b->chains == 2 &&
+      (hipStreamCreateWithFlags(&b->stream2, hipStreamNonBlocking) != hipSuccess ||
+       hipEventCreateWithFlags(&b->ev_lag, hipEventDisableTiming) != hipSuccess ||
+       hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming) != hipSuccess)) {
+    (void)hipGetLastError();
+    tbs_batch_destroy(b);
+    return fail(nullptr, TBS_ERR_HIP, "batch second stream/events");
+  }
+  // balance the chains by work (points x right-hand sides), largest first
+  b->chain_of.assign(nplans, 0);
+  if (b->chains == 2) {
+    std::vector<int> order(nplans);
+    for (int i = 0; i < nplans; ++i) order[i] = i;
+    auto work = [&](int i) { return (double)b->plans[i]->M[0] * b->plans[i]->M[1] * b->plans[i]->batch; };
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work(x) > work(y); });
+    double w[2] = {0.0, 0.0};
+    for (int i : order) {
+      const int c = w[1] < w[0] ? 1 : 0;
+      b->chain_of[i] = c;
+      w[c] += work(i);
+    }
+  }
   // group by padded length (rows: M_x; columns: M_y and the column shape)
   b->rpos.assign(nplans, 0);
   b->cpos.assign(nplans, 0);
-  auto find_or_add = [](std::vector<tbs_batch::Group>& gs, int M, int cb, int nc, int nr) -> tbs_batch::Group& {
+  auto find_or_add = [](std::vector<tbs_batch::Group>& gs, int chain, int M, int cb, int nc,
+                        int nr) -> tbs_batch::Group& {
     for (auto& g : gs)
-      if (g.M == M && g.cb == cb && g.nc == nc && g.nr == nr) return g;
+      if (g.chain == chain && g.M == M && g.cb == cb && g.nc == nc && g.nr == nr) return g;
     gs.push_back(tbs_batch::Group());
+    gs.back().chain = chain;
     gs.back().M = M;
     gs.back().cb = cb;
     gs.back().nc = nc;
@@ -1387,10 +1460,10 @@ int tbs_batch_create(tbs_batch** out, tbs_plan* const* plans, int nplans) {
   };
   for (int i = 0; i < nplans; ++i) {
     tbs_plan* p = b->plans[i];
-    find_or_add(b->rgroups, (int)p->M[0], p->cb, 0, p->row_nr).members.push_back(i);
+    find_or_add(b->rgroups, b->chain_of[i], (int)p->M[0], p->cb, 0, p->row_nr).members.push_back(i);
     int nc = 0;
     (void)make_conv2d_args(p, false, &nc);
-    find_or_add(b->cgroups, (int)p->M[1], p->cb, nc, 0).members.push_back(i);
+    find_or_add(b->cgroups, b->chain_of[i], (int)p->M[1], p->cb, nc, 0).members.push_back(i);
   }
   std::vector<int> starts;
   int pos = 0;
@@ -1446,7 +1519,12 @@ int tbs_batch_solve(tbs_batch* b, const void* const* sources, const void* const*
     key.push_back(p_outs[i]);
   }
   for (tbs_plan* p : b->plans) key.push_back(p->ghat);
-  if (!(b->exec && key == b->key && L == b->key_L)) {
+  const bool ready = b->exec != nullptr && key == b->key && L == b->key_L;
+  if (!ready) {
+    // a previous solve may still read the descriptor tables
+    if (hipStreamSynchronize(b->stream) != hipSuccess ||
+        (b->stream2 && hipStreamSynchronize(b->stream2) != hipSuccess))
+      return bfail(b, TBS_ERR_HIP, "batch: previous solve failed");
     batch_drop_graph(b);
     // per-plan scratch for L terms, then the descriptor tables
     for (tbs_plan* p : b->plans) {
@@ -1548,6 +1626,10 @@ void tbs_batch_destroy(tbs_batch* b) {
   batch_free_tables(b);
   if (b->ev_in) (void)hipEventDestroy(b->ev_in);
   if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+  if (b->stream2) (void)hipStreamSynchronize(b->stream2);
+  if (b->ev_lag) (void)hipEventDestroy(b->ev_lag);
+  if (b->ev_join) (void)hipEventDestroy(b->ev_join);
+  if (b->stream2) (void)hipStreamDestroy(b->stream2);
   if (b->stream) (void)hipStreamDestroy(b->stream);
   delete b;
 }
