@@ -483,6 +483,73 @@ def test_cbs_weak_scatterer_agrees_with_tbs_limit():
     assert rel(b, oracle.periodic_helmholtz_dense(k2, dx, s)) < 1e-9
 
 
+# ------------------------------------------------------- density contrast --
+
+def test_density_operator_discrete_symbol():
+    """On a constant gamma, D acts on sin(a x) sin(b y) at interior cells as
+    gamma times the discrete Laplacian symbol -(4/dx^2)(sin^2(a dx/2) +
+    sin^2(b dx/2)) (a closed form), which tends to -gamma (a^2 + b^2)."""
+    n, dx, gam = 40, 0.3, 0.7
+    a, b = 0.9, 1.7
+    y, x = np.mgrid[0:n, 0:n] * dx
+    u = np.sin(a * x) * np.sin(b * y)
+    D = oracle.density_operator(np.full((n, n), gam), dx, u)
+    sym = -(4.0 / dx ** 2) * (np.sin(a * dx / 2) ** 2 + np.sin(b * dx / 2) ** 2)
+    inner = (slice(1, -1), slice(1, -1))
+    assert np.allclose(D[inner], gam * sym * u[inner], rtol=0, atol=1e-12)
+
+
+def test_density_operator_second_order_variable_coefficient():
+    """Smooth gamma and u: D(u) converges to div(gamma grad u) (analytic) at
+    second order in dx."""
+    errs = []
+    for n in (32, 64, 128):
+        dx = 4.0 / n
+        y, x = np.mgrid[0:n, 0:n] * dx + dx / 2
+        gam = 0.3 * np.exp(-((x - 2) ** 2 + (y - 2) ** 2))
+        u = np.exp(1j * (1.3 * x + 0.4 * y)) * np.exp(-((x - 2) ** 2 + (y - 2) ** 2) / 2)
+        # analytic div(gamma grad u) with complex u (symbolic derivatives written out)
+        gx = gam * (-2 * (x - 2)); gy = gam * (-2 * (y - 2))
+        ux = u * (1.3j - (x - 2)); uy = u * (0.4j - (y - 2))
+        uxx = ux * (1.3j - (x - 2)) - u; uyy = uy * (0.4j - (y - 2)) - u
+        exact = gx * ux + gy * uy + gam * (uxx + uyy)
+        D = oracle.density_operator(gam, dx, u)
+        inner = (slice(n // 8, -n // 8), slice(n // 8, -n // 8))
+        errs.append(np.max(np.abs(D[inner] - exact[inner])) / np.max(np.abs(exact[inner])))
+    assert errs[1] < 0.3 * errs[0] and errs[2] < 0.3 * errs[1], errs
+
+
+def test_density_operator_symmetric_negative():
+    """Summation by parts: the matrix of D is real symmetric and negative
+    semidefinite for gamma >= 0 (the term is self-adjoint)."""
+    rng = np.random.default_rng(4)
+    gam = rng.uniform(0, 0.4, (7, 9))
+    Dm = oracle.density_matrix(gam, 0.5)
+    assert np.allclose(Dm, Dm.T, atol=1e-14)
+    assert np.max(np.linalg.eigvalsh(Dm)) < 1e-12
+
+
+def test_density_series_converges_to_dense_solve():
+    """With a weak density and speed contrast the series converges to the
+    dense solution of p = G (V - D) p + G s."""
+    grid = (10, 11)
+    dx = 1.0
+    k0 = 2 * np.pi / 6 * (1 + 0.03j)
+    V = 0.05 * (k0 * k0).real * workloads.random_field(grid, 21).real
+    yy, xx = np.mgrid[0:grid[0], 0:grid[1]]
+    gam = 0.06 * np.exp(-((yy - 5) ** 2 + (xx - 5) ** 2) / 6.0)
+    s = workloads.random_field(grid, 22)
+    A = oracle.dense_operator(k0, dx, grid)
+    Dm = oracle.density_matrix(gam, dx)
+    K = A @ (np.diag(V.ravel()) - Dm)
+    exact = np.linalg.solve(np.eye(K.shape[0]) - K, A @ s.ravel()).reshape(grid)
+    rho = np.max(np.abs(np.linalg.eigvals(K)))
+    assert rho < 0.6
+    p, res = oracle.solve_density(k0, dx, s, V, gam, 60)
+    assert rel(p, exact) < 1e-9
+    assert res[-1] < 1e-9
+
+
 # ---------------------------------------------------------------- adjoint ---
 
 def test_adjoint_green_operator_dot_product():
