@@ -204,6 +204,21 @@ int tbs_harmonic_source(tbs_plan *plan, const void *p1_dev, const double *c_dev,
 int tbs_harmonic_source_n(tbs_plan *plan, int n, const void *const *fields_dev, const double *c_dev,
                           double omega, double rho, double BA, void *S_dev);
 
+/* Attach a density contrast to a 2D padded plan (NULL detaches): the term
+ * div(gamma grad psi) of the inhomogeneous wave equation (Sec. 2.1.3, Eqs.
+ * acoustic_waveequn_time_dependent_inhomogeneous and mismatch_parameters,
+ * gamma = (rho_s - rho_f) / rho_s; the paper drops it for rho_s ~ rho_f)
+ * joins the potential of every term: u_n = G(V u_{n-1} - div(gamma grad
+ * u_{n-1})), in conservative second-order differences with gamma at the half
+ * points the mean of the two cells and zero outside the grid.
+ *   gamma_dev: dev float64 [N_y][N_x], owned by the caller, read by every
+ *              later tbs_solve until detached (the potential of tbs_solve
+ *              may then be NULL: V = 0).
+ * Each term then takes one more row pass (the field is kept in space between
+ * them).  TBS_ERR_UNSUPPORTED on 3D or periodic plans; tbs_adjoint and
+ * tbs_batch_create refuse plans with a density contrast. */
+int tbs_density_contrast(tbs_plan *plan, const double *gamma_dev);
+
 /* ---- the paper's periodic scheme (periodic plans, padding 1) ----------- */
 
 /* Tabulate the periodic spectrum g~(p) = 1 / (|p|^2 - k0^2 - i eps) (Sec. 2.2,

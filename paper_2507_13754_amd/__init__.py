@@ -36,7 +36,7 @@ EXPORTS = (
     "tbs_speed_gradient", "tbs_profile_enable", "tbs_profile_read", "tbs_plan_destroy",
     "tbs_last_error", "tbs_batch_create", "tbs_batch_solve", "tbs_batch_destroy",
     "tbs_batch_last_error", "tbs_plan_autotune", "tbs_green_periodic", "tbs_abl_profile",
-    "tbs_kspace_coefficients",
+    "tbs_kspace_coefficients", "tbs_density_contrast",
     "tbs_iterate",
 )
 PASS_KINDS = ("row_first", "row_mid", "row_last", "col_conv", "col_fwd", "col_inv")
@@ -106,6 +106,7 @@ def library() -> ctypes.CDLL:
         "tbs_last_error": (ctypes.c_char_p, [vp]),
         "tbs_green_periodic": (ctypes.c_int, [vp, ctypes.c_double, vp]),
         "tbs_kspace_coefficients": (ctypes.c_int, [ctypes.c_double] * 4 + [vp]),
+        "tbs_density_contrast": (ctypes.c_int, [vp, vp]),
         "tbs_abl_profile": (ctypes.c_int, [ctypes.c_int64, ctypes.c_double, ctypes.c_double,
                                            ctypes.c_double, dp]),
         "tbs_iterate": (ctypes.c_int, [vp, vp, vp, vp, vp, ctypes.c_int, ctypes.c_double, ctypes.c_int,
@@ -365,6 +366,15 @@ class Plan:
         _check(library().tbs_harmonic_source_n(self._h, int(n), ptrs, cp, omega, rho, BA, op), self._h,
                "tbs_harmonic_source_n")
         return out
+
+    def density_contrast(self, gamma=None):
+        """Attach (float64 device map, shape of the grid) or detach (None) the
+        density-contrast term; the tensor is kept alive by the plan."""
+        torch = _torch()
+        gp = _ptr(gamma, torch.float64, self.shape, "gamma")
+        _check(library().tbs_density_contrast(self._h, gp), self._h, "tbs_density_contrast")
+        self._gamma = gamma
+        return self
 
     # -- the paper's periodic scheme (plans made with padding=1) --
     def green_periodic(self, eps: float, vv: Optional[KSpacePotential] = None):

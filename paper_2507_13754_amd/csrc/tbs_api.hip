@@ -63,6 +63,11 @@ struct tbs_plan {
   size_t jpart_cap = 0;
   int64_t device_bytes = 0;
   bool green_ready = false;
+  // density contrast (2D padded plans): caller's float64 [N_y][N_x] map, and
+  // the term kept in space between the two row passes of a term
+  const double* gamma = nullptr;
+  void* ubuf = nullptr;
+  size_t ubuf_bytes = 0;
   // periodic (unpadded) plans of the paper's own scheme
   bool periodic = false;
   void* ghat_vv = nullptr;  // g~ VV (Case II k-space potential) or NULL
@@ -440,13 +445,44 @@ int forward_series(tbs_plan* p, const void* source, const void* V, int L, void* 
   rc = ensure_doubles(p, &p->resid, &p->resid_cap, (size_t)p->batch * L);
   if (rc) return rc;
   const size_t slot = (size_t)p->batch * p->P * p->esz;
-  const int Leff = V ? L : 1;  // V = 0: u_n = 0 for n >= 1
+  const int Leff = (V || p->gamma) ? L : 1;  // V = 0 and no density: u_n = 0 for n >= 1
   // u_0 = G s
   rc = run_row(p, tbs::ROW_IN_SOURCE, tbs::ACC_NONE, 1, false, source, nullptr, nullptr, nullptr,
                nullptr, nullptr, nullptr);
   if (rc) return rc;
   rc = run_cols(p, false);
   if (rc) return rc;
+  if (p->gamma) {
+    // density contrast: each term's field is kept in space, then a second row
+    // pass forms V u - div(gamma grad u) (it needs the neighbouring rows)
+    if (p->ubuf_bytes < slot) {
+      dev_free(p, p->ubuf, p->ubuf_bytes);
+      p->ubuf_bytes = 0;
+      rc = dev_alloc(p, &p->ubuf, slot);
+      if (rc) return rc;
+      p->ubuf_bytes = slot;
+    }
+    for (int n = 1; n <= L; ++n) {
+      void* st = (pstore && n < L) ? (void*)((char*)pstore + (size_t)(n - 1) * slot) : nullptr;
+      tbs::RowArgs a = make_row_args(p, tbs::ROW_IN_SPECTRAL, n == 1 ? tbs::ACC_INIT : tbs::ACC_ADD, 0,
+                                     false, nullptr, nullptr, p_out, st, nullptr, nullptr,
+                                     p->partials + (size_t)(n - 1) * per_term);
+      a.ustore = n < L ? p->ubuf : nullptr;
+      rc = run_row_args(p, a, n < L ? PK_ROW_MID : PK_ROW_LAST);
+      if (rc) return rc;
+      if (n == L) break;
+      tbs::RowArgs b = make_row_args(p, tbs::ROW_IN_SPATIAL, tbs::ACC_NONE, 1, false, p->ubuf, V,
+                                     nullptr, nullptr, nullptr, nullptr, nullptr);
+      b.gamma = p->gamma;
+      b.inv_dx2 = 1.0 / (p->dx * p->dx);
+      rc = run_row_args(p, b, PK_ROW_FIRST);
+      if (rc) return rc;
+      rc = run_cols(p, false);
+      if (rc) return rc;
+    }
+    TBS_LAUNCH(p, tbs::launch_finish_norms(p->partials, L, L, p->batch, nblk, p->resid, p->stream));
+    return TBS_OK;
+  }
   for (int n = 1; n < Leff; ++n) {
     void* st = pstore ? (void*)((char*)pstore + (size_t)(n - 1) * slot) : nullptr;
     rc = run_row(p, tbs::ROW_IN_SPECTRAL, n == 1 ? tbs::ACC_INIT : tbs::ACC_ADD, 1, false,
@@ -790,6 +826,7 @@ void tbs_plan_destroy(tbs_plan* p) {
   dev_free(p, q, 0);
   dev_free(p, p->ghat_vv, 0);
   dev_free(p, p->psi0, 0);
+  dev_free(p, p->ubuf, 0);
   q = p->iflags;
   dev_free(p, q, 0);
   q = p->ierrs;
@@ -951,6 +988,14 @@ int tbs_green_tabulate(tbs_plan* p) {
   cleanup();
   if (he != hipSuccess) return hip_fail(p, he, "green tabulation");
   p->green_ready = true;
+  return TBS_OK;
+}
+
+int tbs_density_contrast(tbs_plan* p, const double* gamma) {
+  if (!p) return TBS_ERR_INVALID;
+  if (p->periodic || p->ndim != 2)
+    return fail(p, TBS_ERR_UNSUPPORTED, "the density term is built for 2D padded plans");
+  p->gamma = gamma;
   return TBS_OK;
 }
 
@@ -1177,6 +1222,7 @@ int tbs_adjoint(tbs_plan* p, const void* source, const void* V, int L, const voi
                 double* residual_out, int flags) {
   int rc = check_plan_ready(p);
   if (rc) return rc;
+  if (p->gamma) return fail(p, TBS_ERR_UNSUPPORTED, "no adjoint with a density contrast");
   if (!source || !V || !q || !grad) return fail(p, TBS_ERR_INVALID, "NULL argument");
   if (L < 1 || L > 100000) return fail(p, TBS_ERR_INVALID, "nterms must be >= 1");
   if (flags != TBS_ADJ_STORE && flags != TBS_ADJ_RECOMPUTE)
@@ -1400,7 +1446,7 @@ int tbs_batch_create(tbs_batch** out, tbs_plan* const* plans, int nplans) {
   if (!b) return fail(nullptr, TBS_ERR_OOM, "host allocation failed");
   for (int i = 0; i < nplans; ++i) {
     tbs_plan* p = plans[i];
-    if (!p || p->ndim != 2 || p->periodic || !p->green_ready || p->fp64 != plans[0]->fp64) {
+    if (!p || p->ndim != 2 || p->periodic || p->gamma || !p->green_ready || p->fp64 != plans[0]->fp64) {
       delete b;
       return fail(nullptr, TBS_ERR_INVALID,
                   "batch plans must be 2D, tabulated and of one dtype");

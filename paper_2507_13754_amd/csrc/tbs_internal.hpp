@@ -36,6 +36,10 @@ struct RowArgs {
   int in_mode, acc, out_spec, conj_v;
   int cb;
   int xcd_remap;
+  // ROW_IN_SPATIAL (2D): subtract the density term div(gamma grad src) when
+  // gamma (float64 [ny][nx]) is set; inv_dx2 = 1 / dx^2
+  const double* gamma;
+  double inv_dx2;
 };
 
 struct ColArgs {

@@ -92,6 +92,34 @@ __device__ __forceinline__ int mirror_pair(int l, int n) {
   return (l & 1) ? k : n - k;
 }
 
+// Density term div(gamma grad u) at cell (y, x) of a 2D field u (the term of
+// the inhomogeneous wave equation of Sec. 2.1.3 that carries the density
+// contrast gamma = (rho_s - rho_f) / rho_s): conservative second-order
+// differences with gamma at the half points the mean of the two cells, u and
+// gamma zero outside the grid.  c = u(y, x).  FP64 arithmetic.
+template <typename T>
+__device__ __forceinline__ cx<T> density_term(const RowArgs& a, const cx<T>* __restrict__ u,
+                                              int64_t i, int y, int x, cx<T> c) {
+  const double* g = a.gamma;
+  const int64_t gi = (int64_t)y * a.nx + x;
+  const double gc = g[gi];
+  const bool xp = x + 1 < a.nx, xm = x > 0, yp = y + 1 < a.ny, ym = y > 0;
+  const double gxp = 0.5 * (gc + (xp ? g[gi + 1] : 0.0));
+  const double gxm = 0.5 * (gc + (xm ? g[gi - 1] : 0.0));
+  const double gyp = 0.5 * (gc + (yp ? g[gi + a.nx] : 0.0));
+  const double gym = 0.5 * (gc + (ym ? g[gi - a.nx] : 0.0));
+  if (gxp == 0.0 && gxm == 0.0 && gyp == 0.0 && gym == 0.0) return cx<T>{T(0), T(0)};
+  const cx<T> z = {T(0), T(0)};
+  const cx<T> uxp = xp ? u[i + 1] : z, uxm = xm ? u[i - 1] : z;
+  const cx<T> uyp = yp ? u[i + a.nx] : z, uym = ym ? u[i - a.nx] : z;
+  const double cr = c.x, ci = c.y;
+  const double re = gxp * ((double)uxp.x - cr) - gxm * (cr - (double)uxm.x) +
+                    gyp * ((double)uyp.x - cr) - gym * (cr - (double)uym.x);
+  const double im = gxp * ((double)uxp.y - ci) - gxm * (ci - (double)uxm.y) +
+                    gyp * ((double)uyp.y - ci) - gym * (ci - (double)uym.y);
+  return cx<T>{(T)(re * a.inv_dx2), (T)(im * a.inv_dx2)};
+}
+
 // ---------------------------------------------------------------- row pass --
 
 template <typename T, int M, int E, int NR, int CB, bool SPLIT>
@@ -192,8 +220,14 @@ __device__ __forceinline__ void row_pass_body(const RowArgs& a, const int lb) {
       if (j < E / 2 && valid && x < a.nx) {
         w = src[sp_base + x];
         if (a.in_mode == ROW_IN_SPATIAL) {
-          const cx<T> vv = Vp[srow + x];
-          w = a.conj_v ? cmulc(w, vv) : cmul(w, vv);
+          const cx<T> u0 = w;
+          if (Vp != nullptr) {
+            const cx<T> vv = Vp[srow + x];
+            w = a.conj_v ? cmulc(w, vv) : cmul(w, vv);
+          } else {
+            w = cx<T>{T(0), T(0)};
+          }
+          if (a.gamma != nullptr) w = w - density_term(a, src, sp_base + x, yy, x, u0);
         }
       }
       v[j] = w;
