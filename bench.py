@@ -287,6 +287,34 @@ def run_harmonic3d(dev, steps: int, warmup: int, fp64: bool):
     return res
 
 
+def run_density(dev, steps: int, warmup: int):
+    """absorb2d (2048^2, 30 terms, FP32) with a density contrast: the blob map
+    of the medium scaled to gamma_rho = 3 x the speed contrast.  Per term the
+    field is kept in space between two row passes: alg. bytes 112 + 24 B per
+    grid-point-term (u written and read, gamma read)."""
+    import torch
+    import workloads
+    import paper_2507_13754_amd as tbs
+    case = workloads.absorb2d()
+    gam = 3.0 * np.abs(case.c / case.c0 - 1.0)
+    plan = tbs.Plan(case.grid, case.dx, tbs.background_k0(case.omega, case.c0, case.alpha0, case.y),
+                    dtype=torch.complex64).tabulate()
+    plan.autotune()
+    plan.density_contrast(torch.from_numpy(gam).to(dev))
+    V = plan.potential(torch.from_numpy(case.c).to(dev), case.omega, case.c0, case.alpha0, case.y)
+    s = torch.from_numpy(case.sources).to(dev, torch.complex64)
+    out = torch.empty_like(s)
+    ms, _ = time_solves(plan, s, V, case.nterms, out, steps, warmup)
+    plan.close()
+    gpt = case.points * case.nterms
+    nbytes = 136.0 * gpt
+    log(f"[bench] density2d: {ms:.3f} ms/step")
+    return {"workload": "absorb2d (2048^2, 30 terms) with a density contrast gamma_rho = 3 |c/c0 - 1|",
+            "ms_per_step": ms, "value": gpt / (ms * 1e-3), "unit": "grid-point·terms/s",
+            "alg_bytes_per_step": nbytes, "achieved_GBps": nbytes / (ms * 1e-3) / 1e9,
+            "frac": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+
 # the paper's Table 3 (iterations, seconds on its RTX 4060), context only
 PAPER_TABLE3 = {
     "homogeneous": (135, 5.0), "absorbing": (133, 8.0), "absorbing-dispersive": (132, 11.0),
@@ -534,7 +562,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="skip the block-shape autotuner")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
-    ap.add_argument("--extra", default="broadband,harmonic3d,adjoint2d,paper",
+    ap.add_argument("--extra", default="broadband,harmonic3d,adjoint2d,density2d,paper",
                     help="comma-separated side workloads reported in the same line ('' for none)")
     ap.add_argument("--summarize-trace", metavar="DIR",
                     help="write a kernel-trace summary of a rocprofv3 CSV run (no GPU work)")
@@ -677,6 +705,8 @@ def main():
         line["side_workloads"]["harmonic3d"] = run_harmonic3d(dev, max(2, args.steps // 4), 1, not args.no_fp64)
     if "adjoint2d" in extras:
         line["side_workloads"]["adjoint2d"] = run_adjoint2d(dev, 2, 1)
+    if "density2d" in extras:
+        line["side_workloads"]["density2d"] = run_density(dev, max(3, args.steps // 2), 1)
     if "paper" in extras:
         line["side_workloads"]["paper"] = {"c64": run_paper(dev)}
         if not args.no_fp64:
