@@ -73,8 +73,9 @@ enum tbs_iterate_flags {
 };
 
 enum tbs_adjoint_flags {
-  TBS_ADJ_STORE = 0,     /* keep all L-1 forward partial sums in HBM */
-  TBS_ADJ_RECOMPUTE = 1  /* keep ~sqrt(L) checkpoints and recompute segments */
+  TBS_ADJ_STORE = 0,      /* keep all L-1 forward partial sums in HBM */
+  TBS_ADJ_RECOMPUTE = 1,  /* keep ~sqrt(L) checkpoints and recompute segments */
+  TBS_ADJ_SERIES_ONLY = 2 /* only the adjoint field A_L^H q (no gradient pairing) */
 };
 
 /* Library version (major*10000 + minor*100 + patch). */
@@ -284,7 +285,11 @@ int tbs_iterate(tbs_plan *plan, const void *source, const void *potential, const
  *   adj_source : dev [B][P] plan dtype, q (e.g. R^H (R p - p_obs))
  *   grad_out   : dev [B][P] plan dtype, g_V per right-hand side
  *   residual_out: host double [B][L] or NULL: the forward residuals
- *   flags      : TBS_ADJ_STORE or TBS_ADJ_RECOMPUTE
+ *   flags      : TBS_ADJ_STORE or TBS_ADJ_RECOMPUTE; TBS_ADJ_SERIES_ONLY
+ *                writes the adjoint field instead, A_L^H q =
+ *                sum_{m<L} (G^H conj(V))^m G^H q (the adjoint of p = A_L s;
+ *                source may be NULL, potential may be NULL = V 0, and
+ *                residual_out receives that series' residuals)
  * The forward partial sums are recomputed inside the call. */
 int tbs_adjoint(tbs_plan *plan, const void *source, const void *potential, int nterms,
                 const void *adj_source, void *grad_out, double *residual_out, int flags);

@@ -24,7 +24,7 @@ LIB_PATH = os.environ.get("TBS_LIBRARY", os.path.join(HERE, "libtbs.so"))
 TBS_C64, TBS_C128 = 0, 1
 TBS_OK = 0
 TBS_WARN_NONFINITE, TBS_WARN_DIVERGING, TBS_WARN_NOT_CONVERGED = 1, 2, 3
-TBS_ADJ_STORE, TBS_ADJ_RECOMPUTE = 0, 1
+TBS_ADJ_STORE, TBS_ADJ_RECOMPUTE, TBS_ADJ_SERIES_ONLY = 0, 1, 2
 TBS_ITER_PAPER, TBS_ITER_CBS = 0, 1
 
 # Every entry point of include/tbs.h.
@@ -412,7 +412,7 @@ class Plan:
         vp = _ptr(potential, self.dtype, self.shape, "potential")
         qp = _ptr(adj_source, self.dtype, self._bshape(), "adj_source")
         if out is None:
-            out = torch.empty(self._bshape(), dtype=self.dtype, device=source.device)
+            out = torch.empty(self._bshape(), dtype=self.dtype, device=adj_source.device)
         op = _ptr(out, self.dtype, self._bshape(), "out")
         res = np.empty((self.batch, nterms), dtype=np.float64) if residual else None
         self._sync_stream()

@@ -437,7 +437,7 @@ int check_residuals(tbs_plan* p, double* residual_out, int nterms) {
 
 // Forward series.  pstore (optional): slot K-1 receives P_K, K = 1..L-1.
 int forward_series(tbs_plan* p, const void* source, const void* V, int L, void* p_out,
-                   void* pstore) {
+                   void* pstore, bool adj = false) {
   const int nblk = row_blocks(p);
   const size_t per_term = (size_t)2 * p->batch * nblk;
   int rc = ensure_doubles(p, &p->partials, &p->partials_cap, per_term * (size_t)L);
@@ -447,10 +447,10 @@ int forward_series(tbs_plan* p, const void* source, const void* V, int L, void* 
   const size_t slot = (size_t)p->batch * p->P * p->esz;
   const int Leff = (V || p->gamma) ? L : 1;  // V = 0 and no density: u_n = 0 for n >= 1
   // u_0 = G s
-  rc = run_row(p, tbs::ROW_IN_SOURCE, tbs::ACC_NONE, 1, false, source, nullptr, nullptr, nullptr,
+  rc = run_row(p, tbs::ROW_IN_SOURCE, tbs::ACC_NONE, 1, adj, source, nullptr, nullptr, nullptr,
                nullptr, nullptr, nullptr);
   if (rc) return rc;
-  rc = run_cols(p, false);
+  rc = run_cols(p, adj);
   if (rc) return rc;
   if (p->gamma) {
     // density contrast: each term's field is kept in space, then a second row
@@ -485,13 +485,13 @@ int forward_series(tbs_plan* p, const void* source, const void* V, int L, void* 
   }
   for (int n = 1; n < Leff; ++n) {
     void* st = pstore ? (void*)((char*)pstore + (size_t)(n - 1) * slot) : nullptr;
-    rc = run_row(p, tbs::ROW_IN_SPECTRAL, n == 1 ? tbs::ACC_INIT : tbs::ACC_ADD, 1, false,
+    rc = run_row(p, tbs::ROW_IN_SPECTRAL, n == 1 ? tbs::ACC_INIT : tbs::ACC_ADD, 1, adj,
                  nullptr, V, p_out, st, nullptr, nullptr, p->partials + (size_t)(n - 1) * per_term);
     if (rc) return rc;
-    rc = run_cols(p, false);
+    rc = run_cols(p, adj);
     if (rc) return rc;
   }
-  rc = run_row(p, tbs::ROW_IN_SPECTRAL, Leff == 1 ? tbs::ACC_INIT : tbs::ACC_ADD, 0, false,
+  rc = run_row(p, tbs::ROW_IN_SPECTRAL, Leff == 1 ? tbs::ACC_INIT : tbs::ACC_ADD, 0, adj,
                nullptr, nullptr, p_out, nullptr, nullptr, nullptr,
                p->partials + (size_t)(Leff - 1) * per_term);
   if (rc) return rc;
@@ -1223,8 +1223,18 @@ int tbs_adjoint(tbs_plan* p, const void* source, const void* V, int L, const voi
   int rc = check_plan_ready(p);
   if (rc) return rc;
   if (p->gamma) return fail(p, TBS_ERR_UNSUPPORTED, "no adjoint with a density contrast");
-  if (!source || !V || !q || !grad) return fail(p, TBS_ERR_INVALID, "NULL argument");
   if (L < 1 || L > 100000) return fail(p, TBS_ERR_INVALID, "nterms must be >= 1");
+  if (flags == TBS_ADJ_SERIES_ONLY) {
+    // the adjoint field sum_{m<L} (G^H conj(V))^m G^H q: the forward passes
+    // with conj(G^) and conj(V)
+    if (!q || !grad) return fail(p, TBS_ERR_INVALID, "NULL argument");
+    if (grad == q || grad == V) return fail(p, TBS_ERR_INVALID, "grad_out aliases an input");
+    rc = forward_series(p, q, V, L, grad, nullptr, true);
+    if (rc) return rc;
+    if (residual_out) return check_residuals(p, residual_out, L);
+    return TBS_OK;
+  }
+  if (!source || !V || !q || !grad) return fail(p, TBS_ERR_INVALID, "NULL argument");
   if (flags != TBS_ADJ_STORE && flags != TBS_ADJ_RECOMPUTE)
     return fail(p, TBS_ERR_INVALID, "bad flags");
   const size_t slot = (size_t)p->batch * p->P * p->esz;

@@ -182,3 +182,28 @@ def test_second_harmonic_chain(dev, dt, shape):
     assert rel(g2.cpu().numpy(), p2) <= TOL[dt] * 3
     pl1.close()
     pl2.close()
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("shape", [(21, 34), (6, 7, 9)])
+def test_adjoint_field_matches_oracle(dev, dt, shape):
+    """TBS_ADJ_SERIES_ONLY: A_L^H q = sum_m (G^H conj(V))^m G^H q against the
+    oracle's series with G^H and conj(V), and <A_L s, q> = <s, A_L^H q>."""
+    import paper_2507_13754_amd as tbs
+    k0 = 2 * np.pi / 6 * (1 + 0.02j)
+    V = 0.05 * (k0 * k0).real * workloads.random_field(shape, 13)
+    s = workloads.random_field((2,) + shape, 14)
+    q = workloads.random_field((2,) + shape, 15)
+    L = 6
+    G = oracle.GreenOperator(k0, 1.0, shape)
+    ref, _ = oracle.born_series(lambda f: G(f, adjoint=True), q, np.conj(V), L)
+    plan = tbs.Plan(shape, 1.0, k0, dtype=tdt(dt), batch=2).tabulate()
+    w = plan.adjoint(None, to_dev(V, dev, dt), L, to_dev(q, dev, dt), flags=tbs.TBS_ADJ_SERIES_ONLY)
+    w = w.cpu().numpy().astype(np.complex128)
+    assert max(rel(w[b], ref[b]) for b in range(2)) <= TOL[dt]
+    if dt == "c128":
+        p = plan.solve(to_dev(s, dev, dt), to_dev(V, dev, dt), L).cpu().numpy()
+        for b in range(2):
+            lhs, rhs = np.vdot(q[b], p[b]), np.vdot(w[b], s[b])
+            assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+    plan.close()
