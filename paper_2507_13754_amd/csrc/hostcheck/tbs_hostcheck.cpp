@@ -120,3 +120,28 @@ extern "C" int tbs_hostcheck_fft(int M, int E, int inv, const double* in, double
     }
   return 0;
 }
+
+// The closed-form LDS slots of the device exchanges against their definition
+// lpad(index) for every thread, butterfly and output of every stage that
+// exchanges through LDS.  Returns the number of mismatches.
+extern "C" int tbs_hostcheck_slots(int M, int E) {
+  const tbs::Stages st = tbs::make_stages(M, E);
+  if (st.n <= 0 || M % E) return -1;
+  const int TPT = M / E;
+  int bad = 0;
+  for (int t = 0; t < TPT; ++t)
+    for (int j = 0; j < E; ++j)
+      bad += tbs::read_slot(TPT, t, j) != tbs::lpad(t + j * TPT);
+  int L = 1;
+  for (int S = 0; S < st.n; ++S) {
+    const int R = st.r[S];
+    if (S + 1 < st.n && !tbs::stage_is_local(M, E, S))
+      for (int t = 0; t < TPT; ++t)
+        for (int q = 0; q < E / R; ++q)
+          for (int r = 0; r < R; ++r)
+            bad += tbs::write_slot(TPT, L, R, t, q, r) !=
+                   tbs::lpad(tbs::stage_out_index(t + q * TPT, L, R, r));
+    L *= R;
+  }
+  return bad;
+}

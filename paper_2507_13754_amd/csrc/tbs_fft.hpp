@@ -287,8 +287,24 @@ __host__ __device__ constexpr bool stage_is_local(int M, int E, int S) {
 #ifndef TBS_LDS_PAD_SHIFT
 #define TBS_LDS_PAD_SHIFT 4
 #endif
-__device__ __forceinline__ int lpad(int i) { return i + (i >> TBS_LDS_PAD_SHIFT); }
+__host__ __device__ constexpr int lpad(int i) { return i + (i >> TBS_LDS_PAD_SHIFT); }
 __host__ __device__ constexpr int lds_len(int M) { return M + (M >> TBS_LDS_PAD_SHIFT) + 4; }
+
+// The same padded slots written so that the compiler sees one base address
+// per thread plus constant offsets (the ds instructions' immediate field):
+// (x + c) >> s == (x >> s) + (c >> s) whenever c is a multiple of 2^s.
+//   read_slot : lpad(t + j TPT)
+//   write_slot: lpad(stage_out_index(t + q TPT, L, R, r))
+__host__ __device__ constexpr int read_slot(int TPT, int t, int j) {
+  return (TPT % (1 << TBS_LDS_PAD_SHIFT) == 0) ? lpad(t) + j * lpad(TPT) : lpad(t + j * TPT);
+}
+__host__ __device__ constexpr int write_slot(int TPT, int L, int R, int t, int q, int r) {
+  return (L % (1 << TBS_LDS_PAD_SHIFT) == 0 && (TPT * R) % (1 << TBS_LDS_PAD_SHIFT) == 0 && TPT % L == 0)
+             ? lpad((t / L) * L * R + t % L) + q * lpad(TPT * R) + r * lpad(L)
+         : (L == 1 && R == (1 << TBS_LDS_PAD_SHIFT))
+             ? (t + q * TPT) * (R + 1) + r
+             : lpad(stage_out_index(t + q * TPT, L, R, r));
+}
 
 // One Stockham stage S and the exchange to stage S+1 (recursively).
 // SPLIT: exchange real and imaginary parts in two rounds through a scalar LDS
@@ -335,7 +351,7 @@ __device__ __forceinline__ void fft_stages(cx<T> (&v)[E], void* __restrict__ shv
     } else {
       cx<T>* sh = (cx<T>*)shv;
 #pragma unroll
-      for (int r = 0; r < R; ++r) sh[lpad(stage_out_index(b, L, R, r))] = a[r];
+      for (int r = 0; r < R; ++r) sh[write_slot(TPT, L, R, t, q, r)] = a[r];
     }
   }
   if constexpr (LOCAL) {
@@ -347,29 +363,27 @@ __device__ __forceinline__ void fft_stages(cx<T> (&v)[E], void* __restrict__ shv
       T* sh = (T*)shv;
 #pragma unroll
       for (int q = 0; q < NB; ++q) {
-        const int b = t + q * TPT;
 #pragma unroll
-        for (int r = 0; r < R; ++r) sh[lpad(stage_out_index(b, L, R, r))] = v[q + r * NB].x;
+        for (int r = 0; r < R; ++r) sh[write_slot(TPT, L, R, t, q, r)] = v[q + r * NB].x;
       }
       __syncthreads();
 #pragma unroll
-      for (int j = 0; j < E; ++j) v[j].x = sh[lpad(t + j * TPT)];
+      for (int j = 0; j < E; ++j) v[j].x = sh[read_slot(TPT, t, j)];
       __syncthreads();
 #pragma unroll
       for (int q = 0; q < NB; ++q) {
-        const int b = t + q * TPT;
 #pragma unroll
-        for (int r = 0; r < R; ++r) sh[lpad(stage_out_index(b, L, R, r))] = v[q + r * NB].y;
+        for (int r = 0; r < R; ++r) sh[write_slot(TPT, L, R, t, q, r)] = v[q + r * NB].y;
       }
       __syncthreads();
 #pragma unroll
-      for (int j = 0; j < E; ++j) v[j].y = sh[lpad(t + j * TPT)];
+      for (int j = 0; j < E; ++j) v[j].y = sh[read_slot(TPT, t, j)];
       __syncthreads();
     } else {
       cx<T>* sh = (cx<T>*)shv;
       __syncthreads();
 #pragma unroll
-      for (int j = 0; j < E; ++j) v[j] = sh[lpad(t + j * TPT)];
+      for (int j = 0; j < E; ++j) v[j] = sh[read_slot(TPT, t, j)];
       __syncthreads();
     }
     fft_stages<T, M, E, INV, SPLIT, S + 1>(v, shv, tw, t);

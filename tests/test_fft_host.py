@@ -66,3 +66,12 @@ def test_stage_data_flow_is_a_dft(hc, M, E, inv):
     assert nex.value + nloc.value == n - 1
     if n >= 4:
         assert nloc.value >= 1
+
+
+@pytest.mark.parametrize("M,E", [(16, 4), (64, 4), (512, 8), (1024, 16), (2048, 16), (4096, 16), (48, 12),
+                                 (96, 12), (1536, 12), (3072, 12), (80, 20), (640, 20), (1280, 20),
+                                 (2560, 20), (2560, 40), (1536, 24)])
+def test_lds_slot_closed_forms(hc, M, E):
+    """The LDS slots the device code computes as base + constant offsets equal
+    the padded exchange indices they stand for."""
+    assert hc.tbs_hostcheck_slots(M, E) == 0
