@@ -288,7 +288,14 @@ __host__ __device__ constexpr bool stage_is_local(int M, int E, int S) {
 #define TBS_LDS_PAD_SHIFT 4
 #endif
 __host__ __device__ constexpr int lpad(int i) { return i + (i >> TBS_LDS_PAD_SHIFT); }
-__host__ __device__ constexpr int lds_len(int M) { return M + (M >> TBS_LDS_PAD_SHIFT) + 4; }
+// Slots per line of a block: the padded line plus a gap that moves the next
+// line onto other banks (32 banks of 4 bytes, 16 lanes served per cycle for
+// 8-byte accesses).  With 8-byte slots and two lines per block, half of each
+// 16-lane group reads or writes the second line: a gap of 8 slots puts it on
+// the other 16 banks.  Other shapes keep a gap of 4.
+__host__ __device__ constexpr int lds_len(int M, int lines, int esz) {
+  return M + (M >> TBS_LDS_PAD_SHIFT) + ((esz == 8 && lines == 2) ? 8 : 4);
+}
 
 // The same padded slots written so that the compiler sees one base address
 // per thread plus constant offsets (the ds instructions' immediate field):
@@ -392,7 +399,7 @@ __device__ __forceinline__ void fft_stages(cx<T> (&v)[E], void* __restrict__ shv
 
 // Full transform of the thread's E registers (strided layout in and out).
 // Every thread of the block must call it (it contains block barriers).
-// shv: this line's LDS buffer, lds_len(M) elements of T (SPLIT) or cx<T>.
+// shv: this line's LDS buffer, lds_len(M, .) elements of T (SPLIT) or cx<T>.
 template <typename T, int M, int E, bool INV, bool SPLIT>
 __device__ __forceinline__ void fft(cx<T> (&v)[E], void* __restrict__ shv,
                                     const cx<T>* __restrict__ tw, int t) {

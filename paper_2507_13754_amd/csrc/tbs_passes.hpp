@@ -126,7 +126,7 @@ template <typename T, int M, int E, int NR, int CB, bool SPLIT>
 __device__ __forceinline__ void row_pass_body(const RowArgs& a, const int lb) {
   constexpr int TPT = M / E;
   constexpr int NKB = M / CB;
-  constexpr int LD = lds_len(M);
+  constexpr int LD = lds_len(M, NR, SPLIT ? sizeof(T) : 2 * sizeof(T));
   constexpr int NT = NR * TPT;
   constexpr int NW = (NT + 63) / 64;
   static_assert(TPT % CB == 0, "line too short for the column block");
@@ -272,7 +272,7 @@ __device__ __forceinline__ void row_pass_body(const RowArgs& a, const int lb) {
 template <typename T, int M, int E, int NC, int OP, bool SPLIT>
 __device__ __forceinline__ void col_pass_body(const ColArgs& a, const int lb) {
   constexpr int TPT = M / E;
-  constexpr int LD = lds_len(M);
+  constexpr int LD = lds_len(M, NC, SPLIT ? sizeof(T) : 2 * sizeof(T));
   constexpr bool HALF_IN = (OP == COL_CONV || OP == COL_FWD);
   constexpr bool HALF_OUT = (OP == COL_CONV || OP == COL_INV);
   constexpr bool CONV = (OP == COL_CONV || OP == COL_CONV_FULL);
@@ -340,7 +340,8 @@ __device__ __forceinline__ void col_pass_body(const ColArgs& a, const int lb) {
 template <typename T>
 constexpr int lds_waves_per_eu(int M, int E, int lines, bool split) {
   if (!TBS_OCC_HINT) return 1;
-  const long lds = (long)lines * lds_len(M) * (long)(split ? sizeof(T) : 2 * sizeof(T));
+  const int esz = split ? (int)sizeof(T) : 2 * (int)sizeof(T);
+  const long lds = (long)lines * lds_len(M, lines, esz) * esz;
   const int waves_blk = (lines * (M / E) + 63) / 64;
   long blocks = (160L * 1024) / lds;
   if (blocks * waves_blk > 32) blocks = 32 / waves_blk;
@@ -360,7 +361,7 @@ template <typename T, int M, int E, int NR, bool SPLIT>
 __global__ void __launch_bounds__(NR * (M / E)) TBS_OCCUPANCY(T, M, E, NR, SPLIT) k_row_fft_full(cx<T>* data, const cx<T>* tw,
                                                                int nrows, int inverse) {
   constexpr int TPT = M / E;
-  constexpr int LD = lds_len(M);
+  constexpr int LD = lds_len(M, NR, SPLIT ? sizeof(T) : 2 * sizeof(T));
   using LdsT = typename std::conditional<SPLIT, T, cx<T>>::type;
   __shared__ LdsT sh[NR * LD];
   const int tid = threadIdx.x;
@@ -451,13 +452,15 @@ constexpr int rows_per_block(int M, bool fp64) {
               : (M >= 2048 ? TBS_NR_F32 : 4);
 }
 constexpr bool col_fits(int M, int NC, int esz) {
-  return (long)NC * lds_len(M) * (split_lds(M, esz == 16) ? esz / 2 : esz) <= 160L * 1024;
+  const int le = split_lds(M, esz == 16) ? esz / 2 : esz;
+  return (long)NC * lds_len(M, NC, le) * le <= 160L * 1024;
 }
 
 // ------------------------------------------------------ launch templates --
 
 constexpr bool row_fits(int M, int NR, int esz) {
-  return (long)NR * lds_len(M) * (split_lds(M, esz == 16) ? esz / 2 : esz) <= 160L * 1024;
+  const int le = split_lds(M, esz == 16) ? esz / 2 : esz;
+  return (long)NR * lds_len(M, NR, le) * le <= 160L * 1024;
 }
 
 // Row-pass block shapes: the default NR, or (lines of 2048+) 2 or 4 rows when

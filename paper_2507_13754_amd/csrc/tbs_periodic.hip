@@ -25,7 +25,7 @@ __global__ void __launch_bounds__(NR * (M / E)) TBS_OCCUPANCY(T, M, E, NR, SPLIT
   if (a.done != nullptr && *a.done) return;
   constexpr int TPT = M / E;
   constexpr int NKB = M / CB;
-  constexpr int LD = lds_len(M);
+  constexpr int LD = lds_len(M, NR, SPLIT ? sizeof(T) : 2 * sizeof(T));
   constexpr int NT = NR * TPT;
   constexpr int NW = (NT + 63) / 64;
   static_assert(TPT % CB == 0, "line too short for the column block");
