@@ -145,3 +145,37 @@ extern "C" int tbs_hostcheck_slots(int M, int E) {
   }
   return bad;
 }
+
+// The register-resident twiddle factors: for every thread, stage S >= 1,
+// butterfly q and input r, the cache slot the transform reads holds (as
+// tw_load fills it) the table entry of k = (t + q TPT) mod L, and every slot
+// lies inside the cache.  Returns the number of mismatches.
+extern "C" int tbs_hostcheck_twcache(int M, int E) {
+  const tbs::Stages st = tbs::make_stages(M, E);
+  if (st.n <= 0 || M % E) return -1;
+  const int TPT = M / E;
+  const int size = tbs::tw_cache_size(M, E);
+  int bad = 0;
+  for (int t = 0; t < TPT; ++t) {
+    std::vector<int> cache((size_t)size, -1);
+    for (int S = 1; S < st.n; ++S) {  // as tw_load
+      const int R = st.r[S], L = tbs::stage_L(M, E, S), OFF = tbs::stage_twoff(M, E, S);
+      for (int q = 0; q < tbs::tw_classes(M, E, S); ++q)
+        for (int r = 1; r < R; ++r) {
+          const int slot = tbs::tw_cache_base(M, E, S) + q * (R - 1) + r - 1;
+          if (slot < 0 || slot >= size) { ++bad; continue; }
+          cache[(size_t)slot] = OFF + (r - 1) * L + (t + q * TPT) % L;
+        }
+    }
+    for (int S = 1; S < st.n; ++S) {  // as fft_stages reads them
+      const int R = st.r[S], L = tbs::stage_L(M, E, S), OFF = tbs::stage_twoff(M, E, S);
+      for (int q = 0; q < E / R; ++q)
+        for (int r = 1; r < R; ++r) {
+          const int slot = tbs::tw_cache_base(M, E, S) + (q % tbs::tw_classes(M, E, S)) * (R - 1) + r - 1;
+          const int want = OFF + (r - 1) * L + (t + q * TPT) % L;
+          bad += (slot < 0 || slot >= size || cache[(size_t)slot] != want);
+        }
+    }
+  }
+  return bad;
+}

@@ -282,6 +282,29 @@ __host__ __device__ constexpr bool stage_is_local(int M, int E, int S) {
   return S + 1 < make_stages(M, E).n && stage_L(M, E, S) % (M / E) == 0;
 }
 
+// ---- register-resident twiddles -------------------------------------------
+// Butterfly q of stage S >= 1 in thread t twists its inputs by the factors of
+// k = (t + q TPT) mod L.  k depends on q only through q TPT mod L, whose
+// period is L / gcd(TPT, L), so a thread needs tw_classes(S) * (R - 1)
+// factors per stage; a kernel that runs several transforms of one length
+// (forward and inverse use the same factors, conjugated) loads them once.
+__host__ __device__ constexpr int gcd_int(int a, int b) { return b == 0 ? a : gcd_int(b, a % b); }
+__host__ __device__ constexpr int tw_classes(int M, int E, int S) {
+  const int L = stage_L(M, E, S);
+  const int NB = E / make_stages(M, E).r[S];
+  const int P = L / gcd_int(M / E, L);
+  return P < NB ? P : NB;
+}
+__host__ __device__ constexpr int tw_cache_base(int M, int E, int S) {
+  int n = 0;
+  for (int i = 1; i < S; ++i) n += tw_classes(M, E, i) * (make_stages(M, E).r[i] - 1);
+  return n;
+}
+__host__ __device__ constexpr int tw_cache_size(int M, int E) {
+  const int n = tw_cache_base(M, E, make_stages(M, E).n);
+  return n > 0 ? n : 1;
+}
+
 // LDS index with one pad slot per 2^TBS_LDS_PAD_SHIFT elements (breaks
 // power-of-two strides).
 #ifndef TBS_LDS_PAD_SHIFT
@@ -317,9 +340,10 @@ __host__ __device__ constexpr int write_slot(int TPT, int L, int R, int t, int q
 // SPLIT: exchange real and imaginary parts in two rounds through a scalar LDS
 // buffer of M (+pad) values, halving the LDS a line needs (four barriers per
 // exchange instead of two).  Otherwise complex values go through LDS at once.
-template <typename T, int M, int E, bool INV, bool SPLIT, int S>
+// TWC: the twiddle factors come from twc (tw_load), else from the table tw.
+template <typename T, int M, int E, bool INV, bool SPLIT, bool TWC, int S>
 __device__ __forceinline__ void fft_stages(cx<T> (&v)[E], void* __restrict__ shv,
-                                           const cx<T>* __restrict__ tw, int t) {
+                                           const cx<T>* __restrict__ tw, const cx<T>* twc, int t) {
   constexpr Stages st = make_stages(M, E);
   static_assert(st.n > 0, "length not 5-smooth");
   constexpr int R = st.r[S];
@@ -327,6 +351,8 @@ __device__ __forceinline__ void fft_stages(cx<T> (&v)[E], void* __restrict__ shv
   constexpr int TPT = M / E;
   constexpr int NB = E / R;
   constexpr int OFF = stage_twoff(M, E, S);
+  constexpr int TWB = tw_cache_base(M, E, S);
+  constexpr int TWN = tw_classes(M, E, S);
   constexpr bool LAST = (S + 1 == st.n);
   // Once L is a multiple of TPT, output r of butterfly b = t + q TPT lands on
   // index t + j' TPT with j' fixed by (q, r): the reader is the writing thread
@@ -343,7 +369,7 @@ __device__ __forceinline__ void fft_stages(cx<T> (&v)[E], void* __restrict__ shv
     if constexpr (S > 0) {
 #pragma unroll
       for (int r = 1; r < R; ++r) {
-        const cx<T> w = tw[OFF + (r - 1) * L + k];
+        const cx<T> w = TWC ? twc[TWB + (q % TWN) * (R - 1) + r - 1] : tw[OFF + (r - 1) * L + k];
         a[r] = INV ? cmulc(a[r], w) : cmul(a[r], w);
       }
     }
@@ -364,7 +390,7 @@ __device__ __forceinline__ void fft_stages(cx<T> (&v)[E], void* __restrict__ shv
   if constexpr (LOCAL) {
 #pragma unroll
     for (int j = 0; j < E; ++j) v[j] = w[j];
-    fft_stages<T, M, E, INV, SPLIT, S + 1>(v, shv, tw, t);
+    fft_stages<T, M, E, INV, SPLIT, TWC, S + 1>(v, shv, tw, twc, t);
   } else if constexpr (!LAST) {
     if constexpr (SPLIT) {
       T* sh = (T*)shv;
@@ -393,7 +419,7 @@ __device__ __forceinline__ void fft_stages(cx<T> (&v)[E], void* __restrict__ shv
       for (int j = 0; j < E; ++j) v[j] = sh[read_slot(TPT, t, j)];
       __syncthreads();
     }
-    fft_stages<T, M, E, INV, SPLIT, S + 1>(v, shv, tw, t);
+    fft_stages<T, M, E, INV, SPLIT, TWC, S + 1>(v, shv, tw, twc, t);
   }
 }
 
@@ -403,7 +429,34 @@ __device__ __forceinline__ void fft_stages(cx<T> (&v)[E], void* __restrict__ shv
 template <typename T, int M, int E, bool INV, bool SPLIT>
 __device__ __forceinline__ void fft(cx<T> (&v)[E], void* __restrict__ shv,
                                     const cx<T>* __restrict__ tw, int t) {
-  fft_stages<T, M, E, INV, SPLIT, 0>(v, shv, tw, t);
+  fft_stages<T, M, E, INV, SPLIT, false, 0>(v, shv, tw, nullptr, t);
+}
+
+// Loads the factors of stages S.. of thread t into twc (tw_cache_size(M, E)
+// values), in the order fft_stages reads them.
+template <typename T, int M, int E, int S = 1>
+__device__ __forceinline__ void tw_load(cx<T>* twc, const cx<T>* __restrict__ tw, int t) {
+  constexpr Stages st = make_stages(M, E);
+  if constexpr (S < st.n) {
+    constexpr int R = st.r[S];
+    constexpr int L = stage_L(M, E, S);
+    constexpr int OFF = stage_twoff(M, E, S);
+    constexpr int NQ = tw_classes(M, E, S);
+    constexpr int TWB = tw_cache_base(M, E, S);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int k = (t + q * (M / E)) % L;
+#pragma unroll
+      for (int r = 1; r < R; ++r) twc[TWB + q * (R - 1) + r - 1] = tw[OFF + (r - 1) * L + k];
+    }
+    tw_load<T, M, E, S + 1>(twc, tw, t);
+  }
+}
+
+// The transform with the factors already in registers (tw_load).
+template <typename T, int M, int E, bool INV, bool SPLIT>
+__device__ __forceinline__ void fft_cached(cx<T> (&v)[E], void* __restrict__ shv, const cx<T>* twc, int t) {
+  fft_stages<T, M, E, INV, SPLIT, true, 0>(v, shv, nullptr, twc, t);
 }
 
 }  // namespace tbs

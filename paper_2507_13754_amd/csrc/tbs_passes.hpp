@@ -47,6 +47,9 @@
 #ifndef TBS_NC_F64
 #define TBS_NC_F64 2        // columns per FP64 column-convolution block (lines of 2048+)
 #endif
+#ifndef TBS_TW_RESIDENT
+#define TBS_TW_RESIDENT 1   // twiddle factors in registers where they fit
+#endif
 #ifndef TBS_OCC_HINT
 #define TBS_OCC_HINT 1      // size each pass's register budget to its LDS occupancy
 #endif
@@ -120,6 +123,65 @@ __device__ __forceinline__ cx<T> density_term(const RowArgs& a, const cx<T>* __r
   return cx<T>{(T)(re * a.inv_dx2), (T)(im * a.inv_dx2)};
 }
 
+// Waves on the fullest SIMD of a CU when the LDS of one block (LINES lines
+// of length M; 160 KB per CU, 4 SIMDs, at most 8 waves each) limits the
+// blocks a CU holds.
+template <typename T>
+constexpr int lds_only_waves(int M, int E, int lines, bool split) {
+  const int esz = split ? (int)sizeof(T) : 2 * (int)sizeof(T);
+  const long lds = (long)lines * lds_len(M, lines, esz) * esz;
+  const int waves_blk = (lines * (M / E) + 63) / 64;
+  long blocks = (160L * 1024) / lds;
+  if (blocks * waves_blk > 32) blocks = 32 / waves_blk;
+  const int w = (int)((blocks * waves_blk + 3) / 4);  // the fullest SIMD
+  return w < 1 ? 1 : w;
+}
+
+// Whether a pass keeps the twiddle factors of its transforms in registers
+// (loaded once, shared by its forward and inverse transform): for lines of
+// 1024 and more, when the E values and the factors (2 VGPRs per FP32
+// complex, 4 per FP64) plus the rest of the pass fit the registers that the
+// LDS occupancy leaves the waves of the fullest SIMD.  The rest (FP32; twice
+// in FP64) is what the compiled kernels take: about 32 VGPRs in the column
+// pass and 40 in the row pass for power-of-two lines, 80 and 72 for lines
+// with a radix-3 or radix-5 stage.  With these margins no kernel spills more
+// than one register.
+template <typename T>
+constexpr int tw_resident_vgprs(int M, int E, bool row) {
+  const bool odd = (M & (M - 1)) != 0;
+  const int rest = odd ? (row ? 72 : 80) : (row ? 40 : 32);
+  return (int)(sizeof(T) / 2) * (E + tw_cache_size(M, E)) + rest * (int)(sizeof(T) / 4);
+}
+template <typename T>
+constexpr bool tw_resident(int M, int E, int lines, bool split, bool row) {
+  return TBS_TW_RESIDENT && M >= 1024 &&
+         tw_resident_vgprs<T>(M, E, row) <= 512 / lds_only_waves<T>(M, E, lines, split);
+}
+
+// Resident waves per SIMD a pass asks the compiler to budget registers for
+// (512 VGPRs per SIMD lane, shared by its waves): what the LDS allows, but no
+// more than a line of E values per thread can keep in registers without
+// spilling (about 5 E + 40 VGPRs in FP32, twice the values in FP64, at least
+// 112; with resident twiddles the estimate above).  Without the request,
+// lines of 40 values per thread compiled to more than 256 VGPRs: one wave per
+// SIMD.
+// KIND: 0 a kernel without resident twiddles, 1 the row pass, 2 the column pass.
+template <typename T, int KIND>
+constexpr int lds_waves_per_eu(int M, int E, int lines, bool split) {
+  if (!TBS_OCC_HINT) return 1;
+  int w = lds_only_waves<T>(M, E, lines, split);
+  const int need = (sizeof(T) == 8 ? 10 : 5) * E + 40;
+  const int regs = (KIND != 0 && tw_resident<T>(M, E, lines, split, KIND == 1))
+                       ? tw_resident_vgprs<T>(M, E, KIND == 1)
+                       : (need < 112 ? 112 : need);
+  const int wr = 512 / regs;
+  if (w > wr) w = wr;
+  return w < 1 ? 1 : (w > 8 ? 8 : w);
+}
+
+#define TBS_OCCUPANCY(T, M, E, LINES, SPLIT, KIND) \
+  __attribute__((amdgpu_waves_per_eu(lds_waves_per_eu<T, KIND>(M, E, LINES, SPLIT), 8)))
+
 // ---------------------------------------------------------------- row pass --
 
 template <typename T, int M, int E, int NR, int CB, bool SPLIT>
@@ -157,6 +219,9 @@ __device__ __forceinline__ void row_pass_body(const RowArgs& a, const int lb) {
   const int64_t kbstride = (int64_t)a.nrows * CB;
 
   cx<T> v[E];
+  constexpr bool TWR = tw_resident<T>(M, E, NR, SPLIT, true);
+  cx<T> twc[TWR ? tw_cache_size(M, E) : 1];
+  if constexpr (TWR) tw_load<T, M, E>(twc, tw, t);
   double su = 0.0, sp = 0.0;
   if (a.in_mode == ROW_IN_SPECTRAL) {
 #pragma unroll
@@ -164,7 +229,8 @@ __device__ __forceinline__ void row_pass_body(const RowArgs& a, const int lb) {
       const int kx = t + j * TPT;
       v[j] = valid ? X[xbase + (int64_t)(kx / CB) * kbstride + (kx % CB)] : cx<T>{T(0), T(0)};
     }
-    fft<T, M, E, true, SPLIT>(v, shr, tw, t);
+    if constexpr (TWR) fft_cached<T, M, E, true, SPLIT>(v, shr, twc, t);
+    else fft<T, M, E, true, SPLIT>(v, shr, tw, t);
     cx<T>* p = (cx<T>*)a.p;
     const cx<T>* Vp = (const cx<T>*)a.V;
 #pragma unroll
@@ -256,7 +322,8 @@ __device__ __forceinline__ void row_pass_body(const RowArgs& a, const int lb) {
   }
 
   if (a.out_spec) {
-    fft<T, M, E, false, SPLIT>(v, shr, tw, t);
+    if constexpr (TWR) fft_cached<T, M, E, false, SPLIT>(v, shr, twc, t);
+    else fft<T, M, E, false, SPLIT>(v, shr, tw, t);
     if (valid) {
 #pragma unroll
       for (int j = 0; j < E; ++j) {
@@ -303,13 +370,19 @@ __device__ __forceinline__ void col_pass_body(const ColArgs& a, const int lb) {
   const int64_t ob = rhs * a.out_rs + blk * a.out_s1 + i0 * a.out_s0 + c0 + col;
 
   cx<T> v[E];
+  constexpr bool TWR = OP != COL_CONV_FULL && tw_resident<T>(M, E, NC, SPLIT, false);
+  cx<T> twc[TWR ? tw_cache_size(M, E) : 1];
 #pragma unroll
   for (int j = 0; j < E; ++j) {
     const int pos = tt + j * TPT;
     const bool ld = (!HALF_IN || j < E / 2) && cvalid && pos < a.n_in;
     v[j] = ld ? in[ib + pos * a.in_astride] : cx<T>{T(0), T(0)};
   }
-  if constexpr (OP != COL_INV) fft<T, M, E, false, SPLIT>(v, shc, tw, tt);
+  if constexpr (TWR) tw_load<T, M, E>(twc, tw, tt);
+  if constexpr (OP != COL_INV) {
+    if constexpr (TWR) fft_cached<T, M, E, false, SPLIT>(v, shc, twc, tt);
+    else fft<T, M, E, false, SPLIT>(v, shc, tw, tt);
+  }
   if constexpr (CONV) {
     const cx<T>* g = (const cx<T>*)a.ghat;
     const int kx = blk * a.cb + c0 + (col % a.cb);
@@ -320,7 +393,10 @@ __device__ __forceinline__ void col_pass_body(const ColArgs& a, const int lb) {
       v[j] = a.conj_g ? cmulc(v[j], gv) : cmul(v[j], gv);
     }
   }
-  if constexpr (CONV || OP == COL_INV) fft<T, M, E, true, SPLIT>(v, shc, tw, tt);
+  if constexpr (CONV || OP == COL_INV) {
+    if constexpr (TWR) fft_cached<T, M, E, true, SPLIT>(v, shc, twc, tt);
+    else fft<T, M, E, true, SPLIT>(v, shc, tw, tt);
+  }
   if (cvalid) {
 #pragma unroll
     for (int j = 0; j < E; ++j) {
@@ -330,35 +406,9 @@ __device__ __forceinline__ void col_pass_body(const ColArgs& a, const int lb) {
   }
 }
 
-// Resident waves per SIMD a pass asks the compiler to budget registers for
-// (512 VGPRs per SIMD lane, shared by its waves): what the LDS of one block
-// (LINES lines of length M; 160 KB per CU, 4 SIMDs, at most 8 waves each)
-// allows, but no more than a line of E values per thread can keep in
-// registers without spilling (about 5 E + 40 VGPRs in FP32, twice the values
-// in FP64, at least 112).  Without the request, lines of 40 values per
-// thread compiled to more than 256 VGPRs: one wave per SIMD.
-template <typename T>
-constexpr int lds_waves_per_eu(int M, int E, int lines, bool split) {
-  if (!TBS_OCC_HINT) return 1;
-  const int esz = split ? (int)sizeof(T) : 2 * (int)sizeof(T);
-  const long lds = (long)lines * lds_len(M, lines, esz) * esz;
-  const int waves_blk = (lines * (M / E) + 63) / 64;
-  long blocks = (160L * 1024) / lds;
-  if (blocks * waves_blk > 32) blocks = 32 / waves_blk;
-  int w = (int)(blocks * waves_blk / 4);
-  const int need = (sizeof(T) == 8 ? 10 : 5) * E + 40;
-  const int regs = need < 112 ? 112 : need;
-  const int wr = 512 / regs;
-  if (w > wr) w = wr;
-  return w < 1 ? 1 : (w > 8 ? 8 : w);
-}
-
-#define TBS_OCCUPANCY(T, M, E, LINES, SPLIT) \
-  __attribute__((amdgpu_waves_per_eu(lds_waves_per_eu<T>(M, E, LINES, SPLIT), 8)))
-
 // Plain in-place FFT of contiguous rows [nrows][M] (tabulation, FP64).
 template <typename T, int M, int E, int NR, bool SPLIT>
-__global__ void __launch_bounds__(NR * (M / E)) TBS_OCCUPANCY(T, M, E, NR, SPLIT) k_row_fft_full(cx<T>* data, const cx<T>* tw,
+__global__ void __launch_bounds__(NR * (M / E)) TBS_OCCUPANCY(T, M, E, NR, SPLIT, 0) k_row_fft_full(cx<T>* data, const cx<T>* tw,
                                                                int nrows, int inverse) {
   constexpr int TPT = M / E;
   constexpr int LD = lds_len(M, NR, SPLIT ? sizeof(T) : 2 * sizeof(T));
@@ -386,12 +436,12 @@ __global__ void __launch_bounds__(NR * (M / E)) TBS_OCCUPANCY(T, M, E, NR, SPLIT
 // ---------------------------------------------------------------- kernels --
 
 template <typename T, int M, int E, int NR, int CB, bool SPLIT>
-__global__ void __launch_bounds__(NR * (M / E)) TBS_OCCUPANCY(T, M, E, NR, SPLIT) k_row_pass(RowArgs a) {
+__global__ void __launch_bounds__(NR * (M / E)) TBS_OCCUPANCY(T, M, E, NR, SPLIT, 1) k_row_pass(RowArgs a) {
   row_pass_body<T, M, E, NR, CB, SPLIT>(a, xcd_block(blockIdx.x, gridDim.x, a.xcd_remap));
 }
 
 template <typename T, int M, int E, int NC, int OP, bool SPLIT>
-__global__ void __launch_bounds__(NC * (M / E)) TBS_OCCUPANCY(T, M, E, NC, SPLIT) k_col_pass(ColArgs a) {
+__global__ void __launch_bounds__(NC * (M / E)) TBS_OCCUPANCY(T, M, E, NC, SPLIT, 2) k_col_pass(ColArgs a) {
   col_pass_body<T, M, E, NC, OP, SPLIT>(a, xcd_block(blockIdx.x, gridDim.x, a.xcd_remap));
 }
 
@@ -404,7 +454,7 @@ __device__ __forceinline__ int group_of(const int* __restrict__ starts, int ngro
 }
 
 template <typename T, int M, int E, int NR, int CB, bool SPLIT>
-__global__ void __launch_bounds__(NR * (M / E)) TBS_OCCUPANCY(T, M, E, NR, SPLIT)
+__global__ void __launch_bounds__(NR * (M / E)) TBS_OCCUPANCY(T, M, E, NR, SPLIT, 1)
     k_row_pass_group(const RowArgs* __restrict__ descs,
                                                                  const int* __restrict__ starts,
                                                                  int ngroups) {
@@ -414,7 +464,7 @@ __global__ void __launch_bounds__(NR * (M / E)) TBS_OCCUPANCY(T, M, E, NR, SPLIT
 }
 
 template <typename T, int M, int E, int NC, int OP, bool SPLIT>
-__global__ void __launch_bounds__(NC * (M / E)) TBS_OCCUPANCY(T, M, E, NC, SPLIT)
+__global__ void __launch_bounds__(NC * (M / E)) TBS_OCCUPANCY(T, M, E, NC, SPLIT, 2)
     k_col_pass_group(const ColArgs* __restrict__ descs,
                                                                  const int* __restrict__ starts,
                                                                  int ngroups) {

@@ -20,7 +20,7 @@
 namespace tbs {
 
 template <typename T, int M, int E, int NR, int CB, bool SPLIT>
-__global__ void __launch_bounds__(NR * (M / E)) TBS_OCCUPANCY(T, M, E, NR, SPLIT)
+__global__ void __launch_bounds__(NR * (M / E)) TBS_OCCUPANCY(T, M, E, NR, SPLIT, 0)
     k_iter_row(IterArgs a) {
   if (a.done != nullptr && *a.done) return;
   constexpr int TPT = M / E;
@@ -143,7 +143,7 @@ __global__ void __launch_bounds__(NR * (M / E)) TBS_OCCUPANCY(T, M, E, NR, SPLIT
 }
 
 template <typename T, int M, int E, int NC, bool SPLIT>
-__global__ void __launch_bounds__(NC * (M / E)) TBS_OCCUPANCY(T, M, E, NC, SPLIT)
+__global__ void __launch_bounds__(NC * (M / E)) TBS_OCCUPANCY(T, M, E, NC, SPLIT, 0)
     k_iter_col(ColArgs a, const int* done) {
   if (done != nullptr && *done) return;
   col_pass_body<T, M, E, NC, COL_CONV_FULL, SPLIT>(a, xcd_block(blockIdx.x, gridDim.x, a.xcd_remap));

@@ -75,3 +75,13 @@ def test_lds_slot_closed_forms(hc, M, E):
     """The LDS slots the device code computes as base + constant offsets equal
     the padded exchange indices they stand for."""
     assert hc.tbs_hostcheck_slots(M, E) == 0
+
+
+@pytest.mark.parametrize("M,E", [(16, 4), (64, 4), (512, 8), (1024, 16), (2048, 16), (4096, 16), (48, 12),
+                                 (96, 12), (768, 12), (1536, 12), (3072, 12), (80, 20), (640, 20),
+                                 (1280, 20), (2560, 20), (2560, 40), (1536, 24)])
+def test_resident_twiddle_slots(hc, M, E):
+    """A pass that keeps its twiddle factors in registers reads, for every
+    thread, stage, butterfly and input, the factor the table holds for that
+    butterfly: the period of k over the butterflies of a thread is right."""
+    assert hc.tbs_hostcheck_twcache(M, E) == 0
