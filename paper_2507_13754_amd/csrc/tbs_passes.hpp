@@ -50,6 +50,9 @@
 #ifndef TBS_TW_RESIDENT
 #define TBS_TW_RESIDENT 1   // twiddle factors in registers where they fit
 #endif
+#ifndef TBS_TW_MIN_M
+#define TBS_TW_MIN_M 1024   // shortest line that keeps its twiddle factors in registers
+#endif
 #ifndef TBS_OCC_HINT
 #define TBS_OCC_HINT 1      // size each pass's register budget to its LDS occupancy
 #endif
@@ -139,7 +142,7 @@ constexpr int lds_only_waves(int M, int E, int lines, bool split) {
 
 // Whether a pass keeps the twiddle factors of its transforms in registers
 // (loaded once, shared by its forward and inverse transform): for lines of
-// 1024 and more, when the E values and the factors (2 VGPRs per FP32
+// TBS_TW_MIN_M and more, when the E values and the factors (2 VGPRs per FP32
 // complex, 4 per FP64) plus the rest of the pass fit the registers that the
 // LDS occupancy leaves the waves of the fullest SIMD.  The rest (FP32; twice
 // in FP64) is what the compiled kernels take: about 32 VGPRs in the column
@@ -154,7 +157,7 @@ constexpr int tw_resident_vgprs(int M, int E, bool row) {
 }
 template <typename T>
 constexpr bool tw_resident(int M, int E, int lines, bool split, bool row) {
-  return TBS_TW_RESIDENT && M >= 1024 &&
+  return TBS_TW_RESIDENT && M >= TBS_TW_MIN_M &&
          tw_resident_vgprs<T>(M, E, row) <= 512 / lds_only_waves<T>(M, E, lines, split);
 }
 
