@@ -141,14 +141,18 @@ constexpr int lds_only_waves(int M, int E, int lines, bool split) {
 }
 
 // Whether a pass keeps the twiddle factors of its transforms in registers
-// (loaded once, shared by its forward and inverse transform): for lines of
-// TBS_TW_MIN_M and more, when the E values and the factors (2 VGPRs per FP32
-// complex, 4 per FP64) plus the rest of the pass fit the registers that the
-// LDS occupancy leaves the waves of the fullest SIMD.  The rest (FP32; twice
-// in FP64) is what the compiled kernels take: about 32 VGPRs in the column
-// pass and 40 in the row pass for power-of-two lines, 80 and 72 for lines
-// with a radix-3 or radix-5 stage.  With these margins no kernel spills more
-// than one register.
+// (loaded once, shared by its forward and inverse transform).  Row passes:
+// lines of TBS_TW_MIN_M and more, when the E values and the factors (2 VGPRs
+// per FP32 complex, 4 per FP64) plus the rest of the pass fit the registers
+// that the LDS occupancy leaves the waves of the fullest SIMD.  Column passes:
+// lines of half that, also when the factors cost occupancy down to 4 waves
+// per SIMD (128 VGPRs): the 3D z convolution at 512 ran 18 % faster with them
+// at 6 waves than without at 8.  The rest (FP32; twice in FP64) is what the
+// compiled kernels take: about 32 VGPRs in the column pass and 40 in the row
+// pass for power-of-two lines, 80 and 72 for lines with a radix-3 or radix-5
+// stage.  With these margins no kernel spills more than one register.  The
+// forward-only column pass (3D y) keeps loading from the table: it runs one
+// transform, and the lower occupancy made it 5 % slower.
 template <typename T>
 constexpr int tw_resident_vgprs(int M, int E, bool row) {
   const bool odd = (M & (M - 1)) != 0;
@@ -157,8 +161,9 @@ constexpr int tw_resident_vgprs(int M, int E, bool row) {
 }
 template <typename T>
 constexpr bool tw_resident(int M, int E, int lines, bool split, bool row) {
-  return TBS_TW_RESIDENT && M >= TBS_TW_MIN_M &&
-         tw_resident_vgprs<T>(M, E, row) <= 512 / lds_only_waves<T>(M, E, lines, split);
+  const int budget = 512 / lds_only_waves<T>(M, E, lines, split);
+  return TBS_TW_RESIDENT && M >= (row ? TBS_TW_MIN_M : TBS_TW_MIN_M / 2) &&
+         tw_resident_vgprs<T>(M, E, row) <= (row || budget > 128 ? budget : 128);
 }
 
 // Resident waves per SIMD a pass asks the compiler to budget registers for
@@ -373,7 +378,7 @@ __device__ __forceinline__ void col_pass_body(const ColArgs& a, const int lb) {
   const int64_t ob = rhs * a.out_rs + blk * a.out_s1 + i0 * a.out_s0 + c0 + col;
 
   cx<T> v[E];
-  constexpr bool TWR = OP != COL_CONV_FULL && tw_resident<T>(M, E, NC, SPLIT, false);
+  constexpr bool TWR = OP != COL_CONV_FULL && OP != COL_FWD && tw_resident<T>(M, E, NC, SPLIT, false);
   cx<T> twc[TWR ? tw_cache_size(M, E) : 1];
 #pragma unroll
   for (int j = 0; j < E; ++j) {
@@ -444,7 +449,7 @@ __global__ void __launch_bounds__(NR * (M / E)) TBS_OCCUPANCY(T, M, E, NR, SPLIT
 }
 
 template <typename T, int M, int E, int NC, int OP, bool SPLIT>
-__global__ void __launch_bounds__(NC * (M / E)) TBS_OCCUPANCY(T, M, E, NC, SPLIT, 2) k_col_pass(ColArgs a) {
+__global__ void __launch_bounds__(NC * (M / E)) TBS_OCCUPANCY(T, M, E, NC, SPLIT, OP == COL_FWD ? 0 : 2) k_col_pass(ColArgs a) {
   col_pass_body<T, M, E, NC, OP, SPLIT>(a, xcd_block(blockIdx.x, gridDim.x, a.xcd_remap));
 }
 
@@ -467,7 +472,7 @@ __global__ void __launch_bounds__(NR * (M / E)) TBS_OCCUPANCY(T, M, E, NR, SPLIT
 }
 
 template <typename T, int M, int E, int NC, int OP, bool SPLIT>
-__global__ void __launch_bounds__(NC * (M / E)) TBS_OCCUPANCY(T, M, E, NC, SPLIT, 2)
+__global__ void __launch_bounds__(NC * (M / E)) TBS_OCCUPANCY(T, M, E, NC, SPLIT, OP == COL_FWD ? 0 : 2)
     k_col_pass_group(const ColArgs* __restrict__ descs,
                                                                  const int* __restrict__ starts,
                                                                  int ngroups) {
