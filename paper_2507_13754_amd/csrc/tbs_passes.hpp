@@ -51,7 +51,7 @@
 #define TBS_TW_RESIDENT 1   // twiddle factors in registers where they fit
 #endif
 #ifndef TBS_TW_MIN_M
-#define TBS_TW_MIN_M 1024   // shortest line that keeps its twiddle factors in registers
+#define TBS_TW_MIN_M 512    // shortest line that keeps its twiddle factors in registers
 #endif
 #ifndef TBS_OCC_HINT
 #define TBS_OCC_HINT 1      // size each pass's register budget to its LDS occupancy
@@ -141,29 +141,33 @@ constexpr int lds_only_waves(int M, int E, int lines, bool split) {
 }
 
 // Whether a pass keeps the twiddle factors of its transforms in registers
-// (loaded once, shared by its forward and inverse transform).  Row passes:
-// lines of TBS_TW_MIN_M and more, when the E values and the factors (2 VGPRs
-// per FP32 complex, 4 per FP64) plus the rest of the pass fit the registers
-// that the LDS occupancy leaves the waves of the fullest SIMD.  Column passes:
-// lines of half that, also when the factors cost occupancy down to 4 waves
-// per SIMD (128 VGPRs): the 3D z convolution at 512 ran 18 % faster with them
-// at 6 waves than without at 8.  The rest (FP32; twice in FP64) is what the
-// compiled kernels take: about 32 VGPRs in the column pass and 40 in the row
-// pass for power-of-two lines, 80 and 72 for lines with a radix-3 or radix-5
-// stage.  With these margins no kernel spills more than one register.  The
-// forward-only column pass (3D y) keeps loading from the table: it runs one
-// transform, and the lower occupancy made it 5 % slower.
+// (loaded once, shared by its forward and inverse transform): lines of
+// TBS_TW_MIN_M and more, when the E values and the factors (2 VGPRs per FP32
+// complex, 4 per FP64) plus the rest of the pass fit the registers that the
+// LDS occupancy leaves the waves of the fullest SIMD, or at most 128 VGPRs
+// (256 in FP64) where that is more: fewer loads beat the occupancy they cost
+// (the 3D z convolution at 512 ran 18 % faster with the factors at 6 waves per
+// SIMD than without them at 8; its FP64 version 15 % faster).  The rest (FP32;
+// twice in FP64) is what the compiled kernels take: about 32 VGPRs in the
+// column pass and 40 in the row pass (48 at 512) for power-of-two lines, 80
+// and 72 for lines with a radix-3 or radix-5 stage.  With these margins no kernel spills
+// more than one register.  The forward-only column pass (3D y) keeps loading
+// from the table: it runs one transform, and the lower occupancy made it 5 %
+// slower.
 template <typename T>
 constexpr int tw_resident_vgprs(int M, int E, bool row) {
   const bool odd = (M & (M - 1)) != 0;
-  const int rest = odd ? (row ? 72 : 80) : (row ? 40 : 32);
+  const int rest = odd ? (row ? 72 : 80) : (row ? (M <= 512 ? 48 : 40) : 32);
   return (int)(sizeof(T) / 2) * (E + tw_cache_size(M, E)) + rest * (int)(sizeof(T) / 4);
 }
 template <typename T>
 constexpr bool tw_resident(int M, int E, int lines, bool split, bool row) {
   const int budget = 512 / lds_only_waves<T>(M, E, lines, split);
-  return TBS_TW_RESIDENT && M >= (row ? TBS_TW_MIN_M : TBS_TW_MIN_M / 2) &&
-         tw_resident_vgprs<T>(M, E, row) <= (row || budget > 128 ? budget : 128);
+  const int block_waves_simd = (lines * (M / E) + 255) / 256;  // a block's waves share 4 SIMDs
+  const int floor_regs = 128 * (int)(sizeof(T) / 4) < 512 / block_waves_simd
+                             ? 128 * (int)(sizeof(T) / 4) : 512 / block_waves_simd;
+  return TBS_TW_RESIDENT && M >= TBS_TW_MIN_M &&
+         tw_resident_vgprs<T>(M, E, row) <= (budget > floor_regs ? budget : floor_regs);
 }
 
 // Resident waves per SIMD a pass asks the compiler to budget registers for
