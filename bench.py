@@ -46,7 +46,7 @@ def pass_bytes(kind: str, ndim: int, N, M, B: int, esz: int, kahan: bool, ghat_b
     P = N[0] * N[1] * N[2]
     rows = N[1] * N[2]
     X = B * rows * M[0] * esz                 # x-spectral intermediate
-    acc_rw = B * P * esz * (4 if kahan else 2)   # p (and Kahan c) read + write
+    acc_rw = B * P * esz * (3 if kahan else 2)   # p read + write (and Kahan c, bf16 pairs: half size)
     if kind == "row_first":
         return B * P * esz + X
     if kind == "row_mid":
@@ -701,7 +701,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "grid": list(case.grid), "padded": [Mx, My] + ([Mz] if ndim == 3 else []),
                    "nterms": L, "rhs": B, "dx_m": case.dx, "freq_hz": case.freq,
-                   "plan_dtype": "complex64 + Kahan-compensated sum"},
+                   "plan_dtype": "complex64 + Kahan-compensated sum (compensation stored as bf16)"},
         "roofline": roof,
         "step_roofline": {"alg_bytes_per_step": sb32, "achieved_GBps": sb32 / (r32["ms"] * 1e-3) / 1e9,
                           "frac": sb32 / (r32["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,

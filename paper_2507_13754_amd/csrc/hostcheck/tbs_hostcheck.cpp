@@ -4,6 +4,7 @@
 #include <cmath>
 #include <vector>
 
+#include "../tbs_bf16.hpp"
 #include "../tbs_fft.hpp"
 
 namespace {
@@ -178,4 +179,13 @@ extern "C" int tbs_hostcheck_twcache(int M, int E) {
     }
   }
   return bad;
+}
+
+// The bfloat16 storage of the Kahan compensation: out[i] = the 16-bit pattern
+// the device stores for in[i]; back[i] = the value it reads back.
+extern "C" void tbs_hostcheck_bf16(const float* in, int n, uint32_t* out, float* back) {
+  for (int i = 0; i < n; ++i) {
+    out[i] = tbs::bf16_bits(in[i]);
+    back[i] = tbs::bf16_value(out[i]);
+  }
 }

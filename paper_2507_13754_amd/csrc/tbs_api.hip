@@ -47,7 +47,8 @@ struct tbs_plan {
   void* Xadj = nullptr;     // second intermediate (adjoint state while the forward is recomputed)
   size_t X_bytes = 0;
   void* Yb = nullptr;       // 3D y-spectral intermediate [B][M_x/cb][M_y][N_z][cb]
-  void* kc = nullptr;       // Kahan compensation [B][P] (C64)
+  void* kc = nullptr;       // Kahan compensation [B][P] as bf16 (re, im) pairs (C64)
+  size_t kc_bytes = 0;      // its size, rounded up to 8 bytes
   void* ghat = nullptr;     // folded spectrum
   int64_t ghat_n = 0;
   void* tw[3] = {nullptr, nullptr, nullptr};
@@ -700,7 +701,7 @@ int adjoint_recompute(tbs_plan* p, const void* source, const void* V, int L, con
     TBS_HIP(p, hipMemcpyAsync(seg(0), ck_p(c), slot, hipMemcpyDeviceToDevice, p->stream));
     if (hi > lo) {
       TBS_HIP(p, hipMemcpyAsync(pacc, ck_p(c), slot, hipMemcpyDeviceToDevice, p->stream));
-      if (p->kc) TBS_LAUNCH(p, tbs::launch_zero(p->kc, (int64_t)slot, p->stream));
+      if (p->kc) TBS_LAUNCH(p, tbs::launch_zero(p->kc, (int64_t)p->kc_bytes, p->stream));
       tbs::RowArgs a = make_row_args(p, tbs::ROW_IN_SPATIAL, tbs::ACC_NONE, 1, false, ck_u(c), V,
                                      nullptr, nullptr, nullptr, nullptr, nullptr);
       rc = run_row_args(p, a, PK_ROW_FIRST);
@@ -895,7 +896,10 @@ int tbs_plan_create(tbs_plan** out, int ndim, const int64_t grid[3], double dx, 
   int rc = dev_alloc(p, &p->X, p->X_bytes);
   p->xcur = p->X;
   if (!rc && ndim == 3) rc = dev_alloc(p, &p->Yb, B * p->M[0] * p->M[1] * p->N[2] * p->esz);
-  if (!rc && !p->fp64 && !p->periodic) rc = dev_alloc(p, &p->kc, B * p->P * p->esz);
+  if (!rc && !p->fp64 && !p->periodic) {
+    p->kc_bytes = (size_t)((B * p->P * 4 + 7) / 8 * 8);
+    rc = dev_alloc(p, &p->kc, p->kc_bytes);
+  }
   if (!rc && p->periodic) rc = dev_alloc(p, &p->psi0, B * p->P * p->esz);
   if (!rc && p->periodic) rc = dev_alloc(p, (void**)&p->iflags, 2 * sizeof(int));
   p->ghat_n = (p->M[0] / 2 + 1) * (p->M[1] / 2 + 1) * (ndim == 3 ? p->M[2] / 2 + 1 : 1);
@@ -1350,7 +1354,7 @@ int tbs_plan_autotune(tbs_plan* p, int* row_nr_out, int* conv_nc_out) {
         (void)tbs::launch_zero(pacc, (int64_t)slot, p->stream);
         (void)tbs::launch_zero(vz, (int64_t)(p->P * p->esz), p->stream);
         (void)tbs::launch_zero(p->X, (int64_t)p->X_bytes, p->stream);
-        if (p->kc) (void)tbs::launch_zero(p->kc, (int64_t)slot, p->stream);
+        if (p->kc) (void)tbs::launch_zero(p->kc, (int64_t)p->kc_bytes, p->stream);
       }
       auto timeit = [&](auto&& fn) -> double {
         for (int w = 0; w < 2; ++w) fn();

@@ -25,7 +25,7 @@ struct RowArgs {
   void* p;              // accumulator [rhs][P]
   void* pstore;         // optional copy of the updated accumulator [rhs][P]
   void* ustore;         // optional copy of the term u itself [rhs][P]
-  void* c;              // Kahan compensation [rhs][P] (FP32 only)
+  void* c;              // Kahan compensation [rhs][P], bf16 (re, im) pairs in 32 bits (FP32 only)
   const void* pair;     // ACC_PAIR: partial sums P_{L-1-m} [rhs][P]
   void* grad;           // ACC_PAIR: g_V accumulator [rhs][P]
   double* partials;     // [rhs][nblk] x 2 (|u|^2, |p|^2) for this term

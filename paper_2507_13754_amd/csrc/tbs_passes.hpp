@@ -19,6 +19,7 @@
 
 #include <type_traits>
 
+#include "tbs_bf16.hpp"
 #include "tbs_fft.hpp"
 #include "tbs_internal.hpp"
 
@@ -256,18 +257,19 @@ __device__ __forceinline__ void row_pass_body(const RowArgs& a, const int lb) {
         if (a.acc == ACC_INIT) {
           p[i] = u;
           if (a.pstore) ((cx<T>*)a.pstore)[i] = u;
-          if constexpr (sizeof(T) == 4) ((cx<T>*)a.c)[i] = cx<T>{T(0), T(0)};
+          if constexpr (sizeof(T) == 4) ((uint32_t*)a.c)[i] = 0u;
           const double n = norm2(u);
           su += n;
           sp += n;
         } else if (a.acc == ACC_ADD) {
           cx<T> pp = p[i];
           if constexpr (sizeof(T) == 4) {
-            cx<T>* cc = (cx<T>*)a.c;
-            cx<T> ci = cc[i];
+            uint32_t* cc = (uint32_t*)a.c;
+            cx<T> ci;
+            bf16_unpack(cc[i], ci.x, ci.y);
             kahan_add(pp.x, ci.x, u.x);
             kahan_add(pp.y, ci.y, u.y);
-            cc[i] = ci;
+            cc[i] = bf16_pack(ci.x, ci.y);
           } else {
             pp = pp + u;
           }
