@@ -315,7 +315,7 @@ def run_harmonic3d(dev, steps: int, warmup: int, fp64: bool):
 def run_density(dev, steps: int, warmup: int):
     """absorb2d (2048^2, 30 terms, FP32) with a density contrast: the blob map
     of the medium scaled to gamma_rho = 3 x the speed contrast.  Per term the
-    field is kept in space between two row passes: alg. bytes 112 + 24 B per
+    field is kept in space between two row passes: alg. bytes 104 + 24 B per
     grid-point-term (u written and read, gamma read)."""
     import torch
     import workloads
@@ -332,7 +332,7 @@ def run_density(dev, steps: int, warmup: int):
     ms, _ = time_solves(plan, s, V, case.nterms, out, steps, warmup)
     plan.close()
     gpt = case.points * case.nterms
-    nbytes = 136.0 * gpt
+    nbytes = 128.0 * gpt
     log(f"[bench] density2d: {ms:.3f} ms/step")
     return {"workload": "absorb2d (2048^2, 30 terms) with a density contrast gamma_rho = 3 |c/c0 - 1|",
             "ms_per_step": ms, "value": gpt / (ms * 1e-3), "unit": "grid-point·terms/s",

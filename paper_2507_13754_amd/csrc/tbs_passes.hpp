@@ -386,11 +386,20 @@ __device__ __forceinline__ void col_pass_body(const ColArgs& a, const int lb) {
   cx<T> v[E];
   constexpr bool TWR = OP != COL_CONV_FULL && OP != COL_FWD && tw_resident<T>(M, E, NC, SPLIT, false);
   cx<T> twc[TWR ? tw_cache_size(M, E) : 1];
+  constexpr int NLD = HALF_IN ? E / 2 : E;  // registers that can hold input
+  if (cvalid && a.n_in >= NLD * TPT) {
+    // every position of those registers is inside the line (the usual case,
+    // N = M / 2): the same loads without per-lane selects
 #pragma unroll
-  for (int j = 0; j < E; ++j) {
-    const int pos = tt + j * TPT;
-    const bool ld = (!HALF_IN || j < E / 2) && cvalid && pos < a.n_in;
-    v[j] = ld ? in[ib + pos * a.in_astride] : cx<T>{T(0), T(0)};
+    for (int j = 0; j < E; ++j)
+      v[j] = j < NLD ? in[ib + (tt + j * TPT) * a.in_astride] : cx<T>{T(0), T(0)};
+  } else {
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int pos = tt + j * TPT;
+      const bool ld = j < NLD && cvalid && pos < a.n_in;
+      v[j] = ld ? in[ib + pos * a.in_astride] : cx<T>{T(0), T(0)};
+    }
   }
   if constexpr (TWR) tw_load<T, M, E>(twc, tw, tt);
   if constexpr (OP != COL_INV) {
@@ -411,11 +420,15 @@ __device__ __forceinline__ void col_pass_body(const ColArgs& a, const int lb) {
     if constexpr (TWR) fft_cached<T, M, E, true, SPLIT>(v, shc, twc, tt);
     else fft<T, M, E, true, SPLIT>(v, shc, tw, tt);
   }
-  if (cvalid) {
+  constexpr int NST = HALF_OUT ? E / 2 : E;  // registers that can hold output
+  if (cvalid && a.n_out >= NST * TPT) {
 #pragma unroll
-    for (int j = 0; j < E; ++j) {
+    for (int j = 0; j < NST; ++j) out[ob + (tt + j * TPT) * a.out_astride] = v[j];
+  } else if (cvalid) {
+#pragma unroll
+    for (int j = 0; j < NST; ++j) {
       const int pos = tt + j * TPT;
-      if ((!HALF_OUT || j < E / 2) && pos < a.n_out) out[ob + pos * a.out_astride] = v[j];
+      if (pos < a.n_out) out[ob + pos * a.out_astride] = v[j];
     }
   }
 }
