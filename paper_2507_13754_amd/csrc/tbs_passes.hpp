@@ -151,10 +151,11 @@ constexpr int lds_only_waves(int M, int E, int lines, bool split) {
 // SIMD than without them at 8; its FP64 version 15 % faster).  The rest (FP32;
 // twice in FP64) is what the compiled kernels take: about 32 VGPRs in the
 // column pass and 40 in the row pass (48 at 512) for power-of-two lines, 80
-// and 72 for lines with a radix-3 or radix-5 stage.  With these margins no kernel spills
-// more than one register.  The forward-only column pass (3D y) keeps loading
-// from the table: it runs one transform, and the lower occupancy made it 5 %
-// slower.
+// and 72 for lines with a radix-3 or radix-5 stage.  With these margins no
+// kernel spills more than one register, except two FP32 2048 column kernels
+// with the uniform loads of col_pass_body (2 and 6 registers; still the faster
+// variant).  The forward-only column pass (3D y) keeps loading from the
+// table: it runs one transform, and the lower occupancy made it 5 % slower.
 template <typename T>
 constexpr int tw_resident_vgprs(int M, int E, bool row) {
   const bool odd = (M & (M - 1)) != 0;
@@ -387,9 +388,11 @@ __device__ __forceinline__ void col_pass_body(const ColArgs& a, const int lb) {
   constexpr bool TWR = OP != COL_CONV_FULL && OP != COL_FWD && tw_resident<T>(M, E, NC, SPLIT, false);
   cx<T> twc[TWR ? tw_cache_size(M, E) : 1];
   constexpr int NLD = HALF_IN ? E / 2 : E;  // registers that can hold input
-  if (cvalid && a.n_in >= NLD * TPT) {
-    // every position of those registers is inside the line (the usual case,
-    // N = M / 2): the same loads without per-lane selects
+  // FP32 lines of 2048+: when every position of those registers is inside
+  // the line (the usual case, N = M / 2), the same loads without per-lane
+  // selects (shorter lines and FP64 ran slower with the second code path)
+  constexpr bool UNIFORM = sizeof(T) == 4 && M >= 2048;
+  if (UNIFORM && cvalid && a.n_in >= NLD * TPT) {
 #pragma unroll
     for (int j = 0; j < E; ++j)
       v[j] = j < NLD ? in[ib + (tt + j * TPT) * a.in_astride] : cx<T>{T(0), T(0)};
@@ -421,7 +424,7 @@ __device__ __forceinline__ void col_pass_body(const ColArgs& a, const int lb) {
     else fft<T, M, E, true, SPLIT>(v, shc, tw, tt);
   }
   constexpr int NST = HALF_OUT ? E / 2 : E;  // registers that can hold output
-  if (cvalid && a.n_out >= NST * TPT) {
+  if (UNIFORM && cvalid && a.n_out >= NST * TPT) {
 #pragma unroll
     for (int j = 0; j < NST; ++j) out[ob + (tt + j * TPT) * a.out_astride] = v[j];
   } else if (cvalid) {
