@@ -119,6 +119,21 @@ def test_ragged_2d(dev, shape, dt):
 
 
 @pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_long_slowly_converging_series(dev, dt):
+    """150 terms of a series that contracts by about 0.87 per term: the
+    compensated FP32 sum (compensation stored as bfloat16) and the FP64 sum
+    against the oracle, and the series converged."""
+    shape = (96, 96)
+    dx, k0, V, s = small_case(shape, seed=7, contrast=0.2)
+    s = s[:1]
+    L = 150
+    p_ref, r_ref = oracle.solve(k0, dx, s, V, L)
+    assert r_ref[0, 60] < 1e-3 and r_ref[0, -1] < 1e-8
+    p, res = gpu_solve(dev, shape, dx, k0, s, V, L, dt)
+    assert per_rhs_rel(p, p_ref) <= TOL[dt]
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
 @pytest.mark.parametrize("shape", [(9, 10, 12), (16, 16, 16), (5, 3, 33)])
 def test_ragged_3d(dev, shape, dt):
     dx, k0, V, s = small_case(shape, seed=sum(shape), contrast=0.03)
