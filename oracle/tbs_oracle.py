@@ -425,31 +425,45 @@ def abl_mask(shape: Sequence[int], dx: float, zeta_np_per_cm: float, mu_cells: f
 def paper_iterate(gtilde: np.ndarray, s: np.ndarray, V: Optional[np.ndarray] = None,
                   VV: Optional[np.ndarray] = None, mask: Optional[np.ndarray] = None,
                   check_row: Optional[int] = None, tol: float = 1e-5, max_iter: int = 2000):
-    """The paper's iteration (Algorithm 1, one right-hand side ``s``):
-    psi_in = ifft(g~ fft(S)); then repeatedly
-      Cases I, III, IV: psi_fn = ifft(g~ fft(V psi_in + S)) * ABL,
-      Case II:          psi_fn = ifft(g~ (VV fft(psi_in) + fft(S))) * ABL,
-    the error = sum_m |psi_fn[c, m] - psi_in[c, m]| / sum_m |psi_in[c, m]| on
-    the check row c (Sec. 3.1 Eq. Error), stopping at the first iteration
-    whose error is below ``tol`` (the returned count) or after ``max_iter``.
+    """The paper's periodic TBS scheme for one right-hand side ``s``.
+
+    The Lippmann-Schwinger equation psi = G(V psi + S), G = F^-1 g~ F
+    (Sec. 2.2, Eq. TBS_1) is solved as a fixed-point iteration that starts
+    from psi^0 = G S (Eq. TBS_input).  An update applies Eq. TBS_algorithm with
+    the potential of the medium: a pointwise product with V in space (the
+    lossless, inhomogeneous and nonlinear media, Eqs. TBS_solution_lossless and
+    TBS_solution_inhomogeneous) or, for the absorbing-dispersive medium, a
+    product with VV in k-space (Eq. TBS_solution_absorbing-dispersive).  Sec. 3.1
+    multiplies every updated field by the sigmoid absorbing layer ``mask`` and
+    stops once the relative L1 change of the field on the check row (Eq. Error)
+    drops below ``tol``; ``max_iter`` bounds the count.
     Returns (psi, iterations, errors)."""
-    S = np.fft.fft2(s)
-    psi = np.fft.ifft2(gtilde * S)
-    c = s.shape[0] // 2 if check_row is None else check_row
-    errs = []
-    for it in range(1, max_iter + 1):
+    S_hat = np.fft.fft2(s)
+    row = s.shape[0] // 2 if check_row is None else check_row
+
+    def green(f_hat):
+        return np.fft.ifft2(gtilde * f_hat)
+
+    def update(psi):
         if VV is not None:
-            new = np.fft.ifft2(gtilde * (VV * np.fft.fft2(psi) + S))
-        else:
-            new = np.fft.ifft2(gtilde * np.fft.fft2((V if V is not None else 0.0) * psi + s))
+            return green(VV * np.fft.fft2(psi) + S_hat)
+        scattered = 0.0 if V is None else V * psi
+        return green(np.fft.fft2(scattered + s))
+
+    def change(new, old):
+        return float(np.sum(np.abs(new[row] - old[row])) / np.sum(np.abs(old[row])))
+
+    psi = green(S_hat)
+    errs: List[float] = []
+    while len(errs) < max_iter:
+        new = update(psi)
         if mask is not None:
             new = new * mask
-        err = float(np.sum(np.abs(new[c] - psi[c])) / np.sum(np.abs(psi[c])))
-        errs.append(err)
+        errs.append(change(new, psi))
         psi = new
-        if err < tol:
-            return psi, it, np.array(errs)
-    return psi, max_iter, np.array(errs)
+        if errs[-1] < tol:
+            break
+    return psi, len(errs), np.array(errs)
 
 
 def cbs_iterate(gtilde: np.ndarray, s: np.ndarray, V: np.ndarray, eps: float,

@@ -37,6 +37,7 @@ struct tbs_plan {
   int cb = 4;
   int row_nr = 0;           // rows per row-pass block (autotuned; 0 = default)
   int conv_nc = 0;          // columns per convolution block (autotuned; 0 = default)
+  int batch_refs = 0;       // live batches holding this plan (their groups fix row_nr / conv_nc)
   size_t esz = 8;
   int64_t P = 0;
   hipStream_t stream = nullptr;
@@ -545,6 +546,7 @@ struct tbs_batch {
   size_t d_starts_bytes = 0;
   // recorded graph and the arguments it was recorded for
   hipGraphExec_t exec = nullptr;
+  bool counted = false;          // batch_refs of the plans incremented
   std::vector<const void*> key;
   int key_L = 0;
   std::string err;
@@ -999,6 +1001,8 @@ int tbs_density_contrast(tbs_plan* p, const double* gamma) {
   if (!p) return TBS_ERR_INVALID;
   if (p->periodic || p->ndim != 2)
     return fail(p, TBS_ERR_UNSUPPORTED, "the density term is built for 2D padded plans");
+  if (gamma && p->batch_refs > 0)
+    return fail(p, TBS_ERR_STATE, "the plan belongs to a live batch (batches take no density term)");
   p->gamma = gamma;
   return TBS_OK;
 }
@@ -1259,8 +1263,9 @@ int tbs_adjoint(tbs_plan* p, const void* source, const void* V, int L, const voi
   }
   if (flags == TBS_ADJ_RECOMPUTE) return adjoint_recompute(p, source, V, L, q, grad, residual_out);
   // Forward pass keeping the partial sums P_1..P_{L-1} (the final p is not needed).
+  // L-1 partial-sum slots and one more for the running sum
   const size_t need = slot * (size_t)(L - 1);
-  if (p->pstore_bytes < need) {
+  if (p->pstore_bytes < need + slot) {
     dev_free(p, p->pstore, p->pstore_bytes);
     p->pstore_bytes = 0;
     rc = dev_alloc(p, &p->pstore, need + slot);
@@ -1324,6 +1329,8 @@ int tbs_plan_autotune(tbs_plan* p, int* row_nr_out, int* conv_nc_out) {
   if (!p) return TBS_ERR_INVALID;
   if (p->periodic) return fail(p, TBS_ERR_STATE, "periodic plans are not tuned");
   if (!p->green_ready) return fail(p, TBS_ERR_STATE, "tabulate the spectrum before tuning");
+  if (p->batch_refs > 0)
+    return fail(p, TBS_ERR_STATE, "the plan belongs to a live batch (tune before tbs_batch_create)");
   if (p->ndim == 2) {
     static std::mutex mu;
     static std::map<std::vector<int64_t>, std::pair<int, int>> cache;
@@ -1556,10 +1563,11 @@ int tbs_batch_create(tbs_batch** out, tbs_plan* const* plans, int nplans) {
   if (hipMalloc(&b->d_starts, b->d_starts_bytes) != hipSuccess ||
       hipMemcpy(b->d_starts, starts.data(), b->d_starts_bytes, hipMemcpyHostToDevice) != hipSuccess) {
     (void)hipGetLastError();
-    batch_free_tables(b);
-    delete b;
+    tbs_batch_destroy(b);
     return fail(nullptr, TBS_ERR_OOM, "batch tables");
   }
+  for (tbs_plan* p : b->plans) p->batch_refs += 1;
+  b->counted = true;
   *out = b;
   return TBS_OK;
 }
@@ -1578,7 +1586,16 @@ int tbs_batch_solve(tbs_batch* b, const void* const* sources, const void* const*
     key.push_back(potentials[i]);
     key.push_back(p_outs[i]);
   }
-  for (tbs_plan* p : b->plans) key.push_back(p->ghat);
+  // plan-owned buffers and block shapes the recorded launches hold
+  for (tbs_plan* p : b->plans) {
+    key.push_back(p->ghat);
+    key.push_back(p->partials);
+    key.push_back(p->resid);
+    key.push_back(p->X);
+    key.push_back(p->kc);
+    key.push_back((const void*)(intptr_t)p->row_nr);
+    key.push_back((const void*)(intptr_t)p->conv_nc);
+  }
   const bool ready = b->exec != nullptr && key == b->key && L == b->key_L;
   if (!ready) {
     // a previous solve may still read the descriptor tables
@@ -1691,6 +1708,8 @@ void tbs_batch_destroy(tbs_batch* b) {
   if (b->ev_join) (void)hipEventDestroy(b->ev_join);
   if (b->stream2) (void)hipStreamDestroy(b->stream2);
   if (b->stream) (void)hipStreamDestroy(b->stream);
+  if (b->counted)
+    for (tbs_plan* p : b->plans) p->batch_refs -= 1;
   delete b;
 }
 

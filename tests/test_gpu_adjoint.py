@@ -58,6 +58,26 @@ def test_adjoint_series_matches_oracle(dev, dt, shape, L, flags):
     plan.close()
 
 
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_adjoint_store_reuses_one_plan_for_growing_L(dev, dt):
+    """One plan, stored partial sums, L = 4, then 5 (the slot buffer must grow
+    by the running-sum slot too), then 3: each against the oracle."""
+    import paper_2507_13754_amd as tbs
+    shape = (20, 18)
+    k0 = 2 * np.pi / 6 * (1 + 0.02j)
+    V = 0.05 * (k0 * k0).real * workloads.random_field(shape, 11)
+    s = workloads.random_field((2,) + shape, 12)
+    q = workloads.random_field((2,) + shape, 13)
+    G = oracle.GreenOperator(k0, 1.0, shape)
+    plan = tbs.Plan(shape, 1.0, k0, dtype=tdt(dt), batch=2).tabulate()
+    for L in (4, 5, 3):
+        ref = np.stack([oracle.adjoint_series_gradient(G, s[b], V, L, q[b]) for b in range(2)])
+        g = plan.adjoint(to_dev(s, dev, dt), to_dev(V, dev, dt), L, to_dev(q, dev, dt), flags=0)
+        g = g.cpu().numpy().astype(np.complex128)
+        assert max(rel(g[b], ref[b]) for b in range(2)) <= TOL[dt] * (3 if dt == "c64" else 1), L
+    plan.close()
+
+
 def test_adjoint_dot_product_fd_fp64(dev):
     """Re sum dV g_V equals the central difference of Re<q, p_L(V + h dV)>,
     both from the GPU FP64 path."""

@@ -107,3 +107,28 @@ def test_full_size_smallest_broadband_grid(dev):
     p_ref, _ = oracle.solve(k0, c.dx, c.sources, V, c.nterms)
     got = outs[0].cpu().numpy().astype(np.complex128)
     assert max(rel(got[b], p_ref[b]) for b in range(16)) <= TOL["c64"]
+
+
+def test_batch_rerecords_after_member_plan_grows(dev):
+    """A member plan solved alone with more terms reallocates its norm partials;
+    the next batch solve with the old pointers must re-record, not replay into
+    the freed buffer.  Tuning a plan that belongs to a live batch is refused."""
+    import paper_2507_13754_amd as tbs
+    cs = cases(nangles=2, nterms=4)
+    plans, srcs, pots = build(dev, cs, "c64")
+    batch = tbs.Batch(plans)
+    outs = batch.solve(srcs, pots, 4)
+    first = [o.clone() for o in outs]
+    # a much longer single solve grows plans[0]'s partials past the batch's L
+    plans[0].solve(srcs[0], pots[0], 40)
+    torch.cuda.synchronize()
+    outs2, res = batch.solve(srcs, pots, 4, outs=outs, residual=True)
+    for a, b in zip(first, outs2):
+        assert torch.equal(a, b)
+    assert np.all(np.isfinite(res))
+    with pytest.raises(tbs.TBSError):
+        plans[1].autotune()
+    batch.close()
+    plans[1].autotune()          # allowed again once the batch is gone
+    for p in plans:
+        p.close()

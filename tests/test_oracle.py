@@ -255,9 +255,9 @@ def test_paper_constants():
     assert f == pytest.approx(g["frequency_hz"]["value"], rel=g["frequency_hz"]["rtol"])
     kf = 2 * np.pi * g["frequency_hz"]["value"] / prm["v_f"]
     assert kf * prm["a"] == pytest.approx(g["kf_a"]["value"], rel=g["kf_a"]["rtol"])
-    nu, a0, v = prm["nu"], prm["alpha0"], prm["v_f"]
-    assert -2 * a0 * v ** (nu - 1) == pytest.approx(g["tau"]["value"], rel=g["tau"]["rtol"])
-    assert 2 * a0 * v ** nu * math.tan(math.pi * nu / 2) == pytest.approx(g["eta"]["value"], rel=g["eta"]["rtol"])
+    tau, eta = oracle.tau_eta(prm["alpha0"], prm["nu"], prm["v_f"])
+    assert tau == pytest.approx(g["tau"]["value"], rel=g["tau"]["rtol"])
+    assert eta == pytest.approx(g["eta"]["value"], rel=g["eta"]["rtol"])
     assert workloads.alpha0_si(0.75, 1.5) == pytest.approx(g["alpha0_si"]["value"], rel=g["alpha0_si"]["rtol"])
 
 
@@ -288,6 +288,100 @@ def test_wavenumber_absorption_is_power_law(y):
     k = oracle.wavenumber(omega, np.array([1400.0, 1600.0]), a0, y)
     assert np.allclose(k.imag, a0 * omega ** y, rtol=1e-14)
     assert np.allclose(oracle.potential(np.array([1540.0]), omega, 1540.0, a0, y), 0.0, atol=1e-9)
+
+
+def _plane_wave_wavenumber(mult, n):
+    """Wavenumber of the outgoing wave of a point source on a long periodic
+    line in the Case II medium (Sec. 2.3.2): the fixed point of the iteration
+    of Eq. TBS_solution_absorbing-dispersive, psi^ = g~ (VV psi^ + S^), i.e.
+    psi^ = g~ S^ / (1 - g~ VV), with alpha0 = mult x the paper's tissue value.
+    Returns (K fitted from the phase and log-amplitude of psi between two
+    distances, K of oracle.wavenumber)."""
+    f, c, nu = 1.0e6, 1500.0, 1.5
+    om = 2 * np.pi * f
+    dx = c / f / 20
+    k = om / c
+    eps = 0.8 * k * k
+    a0 = mult * 5.5e-10
+    tau, eta = oracle.tau_eta(a0, nu, c)
+    g = oracle.periodic_green_spectrum(k, eps, dx, (n,))
+    VV = oracle.kspace_potential(dx, (n,), om, tau, eta, nu, eps)
+    s = np.zeros(n, np.complex128)
+    s[0] = 1.0 / dx
+    psi = np.fft.ifft(g * np.fft.fft(s) / (1.0 - g * VV))
+    K1 = complex(oracle.wavenumber(om, c, a0, nu))
+    # fit over 0.5 .. 5 decay lengths of the first-order wave
+    i1, i2 = int(0.5 / K1.imag / dx), int(5.0 / K1.imag / dx)
+    x = np.arange(i1, i2) * dx
+    A = np.vstack([x, np.ones_like(x)]).T
+    kr = np.linalg.lstsq(A, np.unwrap(np.angle(psi[i1:i2])), rcond=None)[0][0]
+    ki = -np.linalg.lstsq(A, np.log(np.abs(psi[i1:i2])), rcond=None)[0][0]
+    return complex(kr, ki), K1, k
+
+
+def test_kspace_potential_plane_wave_matches_wavenumber():
+    """Pins the Case II k-space potential VV, tau and eta (Sec. 2.1.2 and
+    Sec. 2.3.2, Eq. TBS_solution_absorbing-dispersive) through the physics of
+    the converged iteration: the eps shift cancels at the fixed point, and the
+    field of a point source is an outgoing wave whose phase advance (Re K,
+    dispersion from eta) and decay (Im K, absorption from tau) equal the
+    plane-wave wavenumber of ``oracle.wavenumber`` (pinned separately by the
+    dispersion relation) up to its first-order error, which falls as alpha0^2.
+    A flipped sign or a missing factor on the tau, eta or eps term changes K
+    at first order."""
+    Ka, K1a, k = _plane_wave_wavenumber(3, 16384)
+    Kb, K1b, _ = _plane_wave_wavenumber(10, 8192)
+    # measured absorption and dispersion agree with the first-order law ...
+    assert abs(Ka.imag - K1a.imag) < 0.03 * K1a.imag
+    assert abs((Ka.real - k) - (K1a.real - k)) < 0.03 * abs(K1a.real - k)
+    # ... and the difference is the second-order remainder
+    ratio = abs(Kb - K1b) / abs(Ka - K1a)
+    assert 8.0 < ratio < 15.0, ratio      # (10/3)^2 = 11.1
+
+
+def _eps_helmholtz_residual(ppw, eps_frac):
+    """Converged (dense Lippmann-Schwinger) field of a smooth source in a
+    smooth absorbing medium, with k0^2 = k(c0)^2 + i eps and V = k^2 - k0^2,
+    checked against the Helmholtz equation with the physical k(x) only."""
+    om, c0, a0, y = 2 * np.pi, 1.0, 0.02, 1.0
+    dx = 1.0 / ppw
+    n = int(round(2.0 / dx))
+    ax = np.meshgrid(*[np.arange(n) * dx] * 2, indexing="ij")
+    xc = (n // 2) * dx
+    f = np.exp(-sum((a - xc) ** 2 for a in ax) / 0.3 ** 2).astype(np.complex128)
+    cmap = c0 * (1 + 0.05 * np.exp(-sum((a - xc - 0.2) ** 2 for a in ax) / 0.4 ** 2))
+    eps = eps_frac * (om / c0) ** 2
+    k0 = oracle.background_k0(om, c0, a0, y, eps)
+    V = oracle.potential(cmap, om, c0, a0, y, eps)
+    p = oracle.dense_ls(oracle.dense_operator(k0, dx, (n, n)), V, f)
+    k = oracle.wavenumber(om, cmap, a0, y)
+    lap = np.zeros_like(p)
+    for axis in range(2):
+        r = lambda s: np.roll(p, s, axis=axis)  # noqa: E731
+        lap += (-r(2) + 16 * r(1) - 30 * p + 16 * r(-1) - r(-2)) / (12 * dx * dx)
+    res = lap + k * k * p + f
+    inner = (slice(3, n - 3),) * 2
+    return float(np.linalg.norm(res[inner]) / np.linalg.norm(f[inner]))
+
+
+def test_potential_eps_shift():
+    """The eps shift of Sec. 2.2 (k0^2 = k_f^2 + i eps) only moves a term
+    between the two sides of the equation: in the background medium the
+    potential is exactly -i eps (Sec. 2.3.1, Eq. TBS_equation_lossless), and the
+    converged field with eps > 0 satisfies the Helmholtz equation of the
+    physical medium (lap p + k(x)^2 p = -f) to O(dx^2), as with eps = 0.  A
+    wrong sign of i eps in either background_k0 or potential leaves an O(1)
+    residual that does not fall with dx."""
+    om, c0, a0, y = 2 * np.pi * 3e6, 1540.0, 2e-10, 1.5
+    kb = complex(oracle.wavenumber(om, c0, a0, y))
+    for eps_frac in (0.3, 0.8):
+        eps = eps_frac * abs(kb) ** 2
+        v = oracle.potential(np.array([c0, c0]), om, c0, a0, y, eps)
+        assert np.all(np.abs(v - (-1j * eps)) <= 1e-13 * abs(kb) ** 2)
+        k0 = oracle.background_k0(om, c0, a0, y, eps)
+        assert k0.imag > kb.imag
+    r1, r2 = _eps_helmholtz_residual(12, 0.5), _eps_helmholtz_residual(24, 0.5)
+    assert r2 < 6e-3 and 3.0 < r1 / r2 < 5.5, (r1, r2)
 
 
 # --------------------------------------------------------------- harmonic ---
@@ -405,7 +499,10 @@ def test_paper_iteration_converges_to_lossless_periodic_solution():
     (Sec. 2.3.1 Eq. TBS_solution_lossless)."""
     dx, k, eps, s = _periodic_case(n=16, seed=7)
     g = oracle.periodic_green_spectrum(k, eps, dx, s.shape)
-    psi, it, errs = oracle.paper_iterate(g, s, V=np.full(s.shape, -1j * eps), tol=1e-13, max_iter=20000)
+    # the homogeneous lossless medium's potential with the eps shift
+    omega = k * 1500.0
+    V = oracle.potential(np.full(s.shape, 1500.0), omega, 1500.0, 0.0, 1.0, eps)
+    psi, it, errs = oracle.paper_iterate(g, s, V=V, tol=1e-13, max_iter=20000)
     axes = [2 * np.pi * np.fft.fftfreq(n, d=dx) for n in s.shape]
     P2 = axes[0][:, None] ** 2 + axes[1][None, :] ** 2
     ref = np.fft.ifft2(np.fft.fft2(s) / (P2 - k * k))
