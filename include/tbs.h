@@ -336,6 +336,28 @@ void tbs_batch_destroy(tbs_batch *batch);
 /* Message of the batch's last failure (NULL-safe). */
 const char *tbs_batch_last_error(const tbs_batch *batch);
 
+/* Per-launch device timing of batched solves (measurement only).  While
+ * enabled, tbs_batch_solve does not replay its graph: it launches the same
+ * grouped kernels directly on the batch stream, the two halves of the work one
+ * after the other, and brackets every launch with two HIP events (results are
+ * bitwise those of the graph).  Enabling (again) or disabling resets the
+ * counters.  Synchronises the batch stream. */
+int tbs_batch_profile_enable(tbs_batch *batch, int enable);
+
+/* Synchronise the batch stream and return the timing since the last read, per
+ * entry e < *nentries: one entry per grouped launch kind, i.e. three per row
+ * group (kind[e] = 0 first row pass, 1 middle row passes, 2 last row pass) and
+ * one per column group (kind[e] = 3 column convolution).  length[e]: the FFT
+ * length of the group's lines; shape[e]: lines per block (rows per row-pass
+ * block, columns per column-pass block); launches[e]: launches timed; ms[e]: summed
+ * event time in ms; the group's plans (indices into the tbs_batch_create
+ * array) are members[first[e] .. first[e+1]).  cap: capacity of kind,
+ * length, shape, launches and ms (first needs cap + 1; members the total count, at
+ * most cap * nplans); *nentries is set even when cap is too small
+ * (TBS_ERR_INVALID then, nothing else written).  Resets the counters. */
+int tbs_batch_profile_read(tbs_batch *batch, int cap, int *nentries, int *kind, int *length, int *shape,
+                           int64_t *launches, double *ms, int *first, int *members);
+
 /* Per-pass device timing.  While enabled, every pass launch is bracketed by
  * two HIP events recorded on the plan's stream.  Pass kinds (index into the
  * output arrays): 0 first row pass (source in), 1 middle row passes,

@@ -37,7 +37,7 @@ EXPORTS = (
     "tbs_last_error", "tbs_batch_create", "tbs_batch_solve", "tbs_batch_destroy",
     "tbs_batch_last_error", "tbs_plan_autotune", "tbs_green_periodic", "tbs_abl_profile",
     "tbs_kspace_coefficients", "tbs_density_contrast",
-    "tbs_iterate",
+    "tbs_iterate", "tbs_batch_profile_enable", "tbs_batch_profile_read",
 )
 PASS_KINDS = ("row_first", "row_mid", "row_last", "col_conv", "col_fwd", "col_inv")
 
@@ -102,6 +102,11 @@ def library() -> ctypes.CDLL:
         "tbs_batch_solve": (ctypes.c_int, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int,
                                            ctypes.POINTER(vp), dp]),
         "tbs_batch_destroy": (None, [vp]),
+        "tbs_batch_profile_enable": (ctypes.c_int, [vp, ctypes.c_int]),
+        "tbs_batch_profile_read": (ctypes.c_int, [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                                  ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                                  ctypes.POINTER(ctypes.c_int), i64p, dp, ctypes.POINTER(ctypes.c_int),
+                                                  ctypes.POINTER(ctypes.c_int)]),
         "tbs_batch_last_error": (ctypes.c_char_p, [vp]),
         "tbs_last_error": (ctypes.c_char_p, [vp]),
         "tbs_green_periodic": (ctypes.c_int, [vp, ctypes.c_double, vp]),
@@ -503,6 +508,35 @@ class Batch:
             warnings.warn(f"tbs_batch_solve: {L.tbs_status_string(rc).decode()}: "
                           f"{L.tbs_batch_last_error(self._h).decode()}", TBSWarning, stacklevel=2)
         return (outs, res) if residual else outs
+
+    def profile(self, enable: bool = True):
+        """Per-launch event timing of later solves (no graph replay meanwhile)."""
+        L = library()
+        rc = L.tbs_batch_profile_enable(self._h, 1 if enable else 0)
+        if rc != TBS_OK:
+            raise TBSError(rc, f"tbs_batch_profile_enable: {L.tbs_batch_last_error(self._h).decode()}")
+
+    def profile_read(self):
+        """Timing since the last read: a list of dicts (kind name, FFT length,
+        launches, summed ms, member plan indices), one per grouped launch kind."""
+        L = library()
+        ne = ctypes.c_int()
+        cap = 4 * len(self.plans) + 8
+        ci = ctypes.c_int
+        kind, length, shape, first = (ci * cap)(), (ci * cap)(), (ci * cap)(), (ci * (cap + 1))()
+        members = (ci * (cap * len(self.plans)))()
+        launches = (ctypes.c_int64 * cap)()
+        ms = (ctypes.c_double * cap)()
+        rc = L.tbs_batch_profile_read(self._h, cap, ctypes.byref(ne), kind, length, shape, launches, ms, first,
+                                      members)
+        if rc != TBS_OK:
+            raise TBSError(rc, f"tbs_batch_profile_read: {L.tbs_batch_last_error(self._h).decode()}")
+        out = []
+        for e in range(ne.value):
+            out.append({"kind": PASS_KINDS[kind[e]], "length": int(length[e]), "shape": int(shape[e]),
+                        "launches": int(launches[e]),
+                        "ms": float(ms[e]), "members": [int(members[i]) for i in range(first[e], first[e + 1])]})
+        return out
 
     def close(self):
         if getattr(self, "_h", None):

@@ -544,11 +544,21 @@ struct tbs_batch {
   void* d_col = nullptr;         // ColArgs [nplans]
   void* d_starts = nullptr;      // int
   size_t d_starts_bytes = 0;
-  // recorded graph and the arguments it was recorded for
+  // descriptor tables and the arguments they were built for; the recorded graph
+  bool tables_ready = false;
   hipGraphExec_t exec = nullptr;
   bool counted = false;          // batch_refs of the plans incremented
   std::vector<const void*> key;
   int key_L = 0;
+  // per-launch event timing (tbs_batch_profile_*): entry 3 g + mode for row
+  // group g (mode 0 first, 1 middle, 2 last row pass), 3 nrg + g for column
+  // group g; marks hold (entry, index of the start event in the pool)
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<std::pair<int, size_t>> marks;
+  std::vector<double> prof_ms;
+  std::vector<int64_t> prof_n;
   std::string err;
 };
 
@@ -570,8 +580,28 @@ void batch_free_tables(tbs_batch* b) {
 void batch_drop_graph(tbs_batch* b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   b->exec = nullptr;
+  b->tables_ready = false;
   b->key.clear();
   b->key_L = 0;
+}
+
+// Start event of a profiled launch (entry e); returns the end event to record
+// after the launch, or nullptr when not profiling (or out of events).
+hipEvent_t batch_prof_begin(tbs_batch* b, int e, hipStream_t s) {
+  if (!b->prof) return nullptr;
+  while (b->ev_used + 2 > b->ev_pool.size()) {
+    hipEvent_t ev;
+    if (hipEventCreate(&ev) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    b->ev_pool.push_back(ev);
+  }
+  const size_t idx = b->ev_used;
+  b->ev_used += 2;
+  if (hipEventRecord(b->ev_pool[idx], s) != hipSuccess) return nullptr;
+  b->marks.push_back({e, idx});
+  return b->ev_pool[idx + 1];
 }
 
 // Enqueue the whole batched series (no synchronisation).  With two chains the
@@ -582,21 +612,28 @@ int batch_enqueue(tbs_batch* b, int L) {
   const tbs::RowArgs* drow = (const tbs::RowArgs*)b->d_row;
   const tbs::ColArgs* dcol = (const tbs::ColArgs*)b->d_col;
   const int* dst = (const int*)b->d_starts;
+  const int nrg = (int)b->rgroups.size();
   auto rows = [&](int chain, int n, hipStream_t s) -> int {
-    for (const auto& g : b->rgroups) {
+    for (int gi = 0; gi < nrg; ++gi) {
+      const auto& g = b->rgroups[gi];
       if (g.chain != chain) continue;
+      hipEvent_t end = batch_prof_begin(b, 3 * gi + (n == 0 ? 0 : (n == L ? 2 : 1)), s);
       int e = tbs::launch_row_group(b->fp64, g.M, g.cb, g.nr, drow + (size_t)n * np + g.first,
                                     dst + g.starts_off, (int)g.members.size(), g.total, s);
       if (e) return bfail(b, TBS_ERR_HIP, std::string("grouped row pass: ") + hipGetErrorString((hipError_t)e));
+      if (end && hipEventRecord(end, s) != hipSuccess) return bfail(b, TBS_ERR_HIP, "profile event");
     }
     return TBS_OK;
   };
   auto cols = [&](int chain, hipStream_t s) -> int {
-    for (const auto& g : b->cgroups) {
+    for (int gi = 0; gi < (int)b->cgroups.size(); ++gi) {
+      const auto& g = b->cgroups[gi];
       if (g.chain != chain) continue;
+      hipEvent_t end = batch_prof_begin(b, 3 * nrg + gi, s);
       int e = tbs::launch_col_group(b->fp64, g.M, g.nc, dcol + g.first, dst + g.starts_off,
                                     (int)g.members.size(), g.total, s);
       if (e) return bfail(b, TBS_ERR_HIP, std::string("grouped column pass: ") + hipGetErrorString((hipError_t)e));
+      if (end && hipEventRecord(end, s) != hipSuccess) return bfail(b, TBS_ERR_HIP, "profile event");
     }
     return TBS_OK;
   };
@@ -612,12 +649,16 @@ int batch_enqueue(tbs_batch* b, int L) {
     }
     return TBS_OK;
   };
-  const bool two = b->chains == 2;
+  // profiled solves run the chains one after the other on one stream, so
+  // that every launch's events bracket that launch alone
+  const bool two = b->chains == 2 && !b->prof;
   int rc = series(0, b->stream, two ? b->ev_lag : nullptr);
   if (!rc && two) {
     if (hipStreamWaitEvent(b->stream2, b->ev_lag, 0) != hipSuccess)
       return bfail(b, TBS_ERR_HIP, "batch chain fork");
     rc = series(1, b->stream2, nullptr);
+  } else if (!rc && b->chains == 2) {
+    rc = series(1, b->stream, nullptr);
   }
   if (rc) return rc;
   for (size_t i = 0; i < b->plans.size(); ++i) {
@@ -1596,7 +1637,7 @@ int tbs_batch_solve(tbs_batch* b, const void* const* sources, const void* const*
     key.push_back((const void*)(intptr_t)p->row_nr);
     key.push_back((const void*)(intptr_t)p->conv_nc);
   }
-  const bool ready = b->exec != nullptr && key == b->key && L == b->key_L;
+  const bool ready = b->tables_ready && key == b->key && L == b->key_L;
   if (!ready) {
     // a previous solve may still read the descriptor tables
     if (hipStreamSynchronize(b->stream) != hipSuccess ||
@@ -1649,6 +1690,19 @@ int tbs_batch_solve(tbs_batch* b, const void* const* sources, const void* const*
         hipMemcpy(b->d_col, cols.data(), cols.size() * sizeof(tbs::ColArgs), hipMemcpyHostToDevice) !=
             hipSuccess)
       return bfail(b, TBS_ERR_HIP, "descriptor upload failed");
+    b->key = key;
+    b->key_L = L;
+    b->tables_ready = true;
+  }
+  const hipStream_t caller = b->plans[0]->stream;
+  if (b->prof) {
+    // profiled: the launches go straight to the batch stream (no graph)
+    hipError_t e = hipEventRecord(b->ev_in, caller);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->ev_in, 0);
+    if (e != hipSuccess) return bfail(b, TBS_ERR_HIP, std::string("batch stream join: ") + hipGetErrorString(e));
+    int rc = batch_enqueue(b, L);
+    if (rc) return rc;
+  } else if (!b->exec) {
     // record the sequence as a graph
     hipGraph_t graph = nullptr;
     if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
@@ -1668,14 +1722,14 @@ int tbs_batch_solve(tbs_batch* b, const void* const* sources, const void* const*
       b->exec = nullptr;
       return bfail(b, TBS_ERR_HIP, std::string("graph instantiation: ") + hipGetErrorString(e));
     }
-    b->key = key;
-    b->key_L = L;
   }
   // caller's stream -> batch stream -> caller's stream
-  const hipStream_t caller = b->plans[0]->stream;
-  hipError_t e = hipEventRecord(b->ev_in, caller);
-  if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->ev_in, 0);
-  if (e == hipSuccess) e = hipGraphLaunch(b->exec, b->stream);
+  hipError_t e = hipSuccess;
+  if (!b->prof) {
+    e = hipEventRecord(b->ev_in, caller);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->ev_in, 0);
+    if (e == hipSuccess) e = hipGraphLaunch(b->exec, b->stream);
+  }
   if (e == hipSuccess) e = hipEventRecord(b->ev_out, b->stream);
   if (e == hipSuccess) e = hipStreamWaitEvent(caller, b->ev_out, 0);
   if (e != hipSuccess) return bfail(b, TBS_ERR_HIP, std::string("graph launch: ") + hipGetErrorString(e));
@@ -1696,9 +1750,64 @@ int tbs_batch_solve(tbs_batch* b, const void* const* sources, const void* const*
   return warn;
 }
 
+int tbs_batch_profile_enable(tbs_batch* b, int enable) {
+  if (!b) return TBS_ERR_INVALID;
+  if (b->stream && hipStreamSynchronize(b->stream) != hipSuccess)
+    return bfail(b, TBS_ERR_HIP, "batch: previous solve failed");
+  b->prof = enable != 0;
+  b->ev_used = 0;
+  b->marks.clear();
+  b->prof_ms.assign(3 * b->rgroups.size() + b->cgroups.size(), 0.0);
+  b->prof_n.assign(b->prof_ms.size(), 0);
+  return TBS_OK;
+}
+
+int tbs_batch_profile_read(tbs_batch* b, int cap, int* nentries, int* kind, int* length, int* shape,
+                           int64_t* launches, double* ms, int* first, int* members) {
+  if (!b || !nentries) return TBS_ERR_INVALID;
+  const int nrg = (int)b->rgroups.size();
+  const int ne = 3 * nrg + (int)b->cgroups.size();
+  *nentries = ne;
+  if (cap < ne) return bfail(b, TBS_ERR_INVALID, "profile arrays too short");
+  if (hipStreamSynchronize(b->stream) != hipSuccess) return bfail(b, TBS_ERR_HIP, "batch: solve failed");
+  if (b->prof_ms.size() != (size_t)ne) {
+    b->prof_ms.assign(ne, 0.0);
+    b->prof_n.assign(ne, 0);
+  }
+  for (const auto& m : b->marks) {
+    float t = 0.0f;
+    if (hipEventElapsedTime(&t, b->ev_pool[m.second], b->ev_pool[m.second + 1]) != hipSuccess)
+      return bfail(b, TBS_ERR_HIP, "profile event time");
+    b->prof_ms[m.first] += t;
+    b->prof_n[m.first] += 1;
+  }
+  b->marks.clear();
+  b->ev_used = 0;
+  int off = 0;
+  for (int e = 0; e < ne; ++e) {
+    const bool row = e < 3 * nrg;
+    const tbs_batch::Group& g = row ? b->rgroups[e / 3] : b->cgroups[e - 3 * nrg];
+    if (kind) kind[e] = row ? e % 3 : 3;
+    if (length) length[e] = g.M;
+    if (shape) shape[e] = row ? (g.nr ? g.nr : tbs::row_rows_per_block(g.M, b->fp64)) : g.nc;
+    if (launches) launches[e] = b->prof_n[e];
+    if (ms) ms[e] = b->prof_ms[e];
+    if (first) first[e] = off;
+    for (int i : g.members) {
+      if (members) members[off] = i;
+      ++off;
+    }
+    b->prof_ms[e] = 0.0;
+    b->prof_n[e] = 0;
+  }
+  if (first) first[ne] = off;
+  return TBS_OK;
+}
+
 void tbs_batch_destroy(tbs_batch* b) {
   if (!b) return;
   if (b->stream) (void)hipStreamSynchronize(b->stream);
+  for (hipEvent_t ev : b->ev_pool) (void)hipEventDestroy(ev);
   batch_drop_graph(b);
   batch_free_tables(b);
   if (b->ev_in) (void)hipEventDestroy(b->ev_in);

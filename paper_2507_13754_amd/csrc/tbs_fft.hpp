@@ -28,6 +28,32 @@ struct cx {
   T x, y;
 };
 
+// Loads and stores of global-memory arrays through address-space-1 pointers.
+// A pass that takes its arguments from a descriptor table in memory (the
+// grouped launches) holds generic pointers whose address space the compiler
+// cannot prove and would access them with flat instructions; a flat access
+// also counts against the LDS wait counter, so every exchange barrier of the
+// transforms would wait for the HBM loads and stores still in flight.
+template <typename T>
+using gvec2 = T __attribute__((ext_vector_type(2)));
+template <typename T>
+__device__ __forceinline__ cx<T> gld(const void* base, int64_t i) {
+  const gvec2<T> r = ((const __attribute__((address_space(1))) gvec2<T>*)(const gvec2<T>*)base)[i];
+  return cx<T>{r.x, r.y};
+}
+template <typename T>
+__device__ __forceinline__ void gst(void* base, int64_t i, cx<T> v) {
+  ((__attribute__((address_space(1))) gvec2<T>*)(gvec2<T>*)base)[i] = gvec2<T>{v.x, v.y};
+}
+template <typename U>
+__device__ __forceinline__ U gld1(const void* base, int64_t i) {
+  return ((const __attribute__((address_space(1))) U*)(const U*)base)[i];
+}
+template <typename U>
+__device__ __forceinline__ void gst1(void* base, int64_t i, U v) {
+  ((__attribute__((address_space(1))) U*)(U*)base)[i] = v;
+}
+
 template <typename T>
 __host__ __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.x + b.x, a.y + b.y}; }
 template <typename T>
@@ -369,7 +395,7 @@ __device__ __forceinline__ void fft_stages(cx<T> (&v)[E], void* __restrict__ shv
     if constexpr (S > 0) {
 #pragma unroll
       for (int r = 1; r < R; ++r) {
-        const cx<T> w = TWC ? twc[TWB + (q % TWN) * (R - 1) + r - 1] : tw[OFF + (r - 1) * L + k];
+        const cx<T> w = TWC ? twc[TWB + (q % TWN) * (R - 1) + r - 1] : gld<T>(tw, OFF + (r - 1) * L + k);
         a[r] = INV ? cmulc(a[r], w) : cmul(a[r], w);
       }
     }
@@ -447,7 +473,7 @@ __device__ __forceinline__ void tw_load(cx<T>* twc, const cx<T>* __restrict__ tw
     for (int q = 0; q < NQ; ++q) {
       const int k = (t + q * (M / E)) % L;
 #pragma unroll
-      for (int r = 1; r < R; ++r) twc[TWB + q * (R - 1) + r - 1] = tw[OFF + (r - 1) * L + k];
+      for (int r = 1; r < R; ++r) twc[TWB + q * (R - 1) + r - 1] = gld<T>(tw, OFF + (r - 1) * L + k);
     }
     tw_load<T, M, E, S + 1>(twc, tw, t);
   }

@@ -105,20 +105,20 @@ __device__ __forceinline__ int mirror_pair(int l, int n) {
 // differences with gamma at the half points the mean of the two cells, u and
 // gamma zero outside the grid.  c = u(y, x).  FP64 arithmetic.
 template <typename T>
-__device__ __forceinline__ cx<T> density_term(const RowArgs& a, const cx<T>* __restrict__ u,
+__device__ __forceinline__ cx<T> density_term(const RowArgs& a, const void* u,
                                               int64_t i, int y, int x, cx<T> c) {
   const double* g = a.gamma;
   const int64_t gi = (int64_t)y * a.nx + x;
-  const double gc = g[gi];
+  const double gc = gld1<double>(g, gi);
   const bool xp = x + 1 < a.nx, xm = x > 0, yp = y + 1 < a.ny, ym = y > 0;
-  const double gxp = 0.5 * (gc + (xp ? g[gi + 1] : 0.0));
-  const double gxm = 0.5 * (gc + (xm ? g[gi - 1] : 0.0));
-  const double gyp = 0.5 * (gc + (yp ? g[gi + a.nx] : 0.0));
-  const double gym = 0.5 * (gc + (ym ? g[gi - a.nx] : 0.0));
+  const double gxp = 0.5 * (gc + (xp ? gld1<double>(g, gi + 1) : 0.0));
+  const double gxm = 0.5 * (gc + (xm ? gld1<double>(g, gi - 1) : 0.0));
+  const double gyp = 0.5 * (gc + (yp ? gld1<double>(g, gi + a.nx) : 0.0));
+  const double gym = 0.5 * (gc + (ym ? gld1<double>(g, gi - a.nx) : 0.0));
   if (gxp == 0.0 && gxm == 0.0 && gyp == 0.0 && gym == 0.0) return cx<T>{T(0), T(0)};
   const cx<T> z = {T(0), T(0)};
-  const cx<T> uxp = xp ? u[i + 1] : z, uxm = xm ? u[i - 1] : z;
-  const cx<T> uyp = yp ? u[i + a.nx] : z, uym = ym ? u[i - a.nx] : z;
+  const cx<T> uxp = xp ? gld<T>(u, i + 1) : z, uxm = xm ? gld<T>(u, i - 1) : z;
+  const cx<T> uyp = yp ? gld<T>(u, i + a.nx) : z, uym = ym ? gld<T>(u, i - a.nx) : z;
   const double cr = c.x, ci = c.y;
   const double re = gxp * ((double)uxp.x - cr) - gxm * (cr - (double)uxm.x) +
                     gyp * ((double)uyp.x - cr) - gym * (cr - (double)uym.x);
@@ -223,7 +223,7 @@ __device__ __forceinline__ void row_pass_body(const RowArgs& a, const int lb) {
   const bool valid = row < a.nrows;
   LdsT* shr = sh + r * LD;
   const cx<T>* tw = (const cx<T>*)a.tw;
-  cx<T>* X = (cx<T>*)a.X;
+  void* X = a.X;
   const int64_t P = (int64_t)a.nrows * a.nx;
   const int yy = valid ? row / a.nz : 0;
   const int zz = valid ? row % a.nz : 0;
@@ -241,12 +241,12 @@ __device__ __forceinline__ void row_pass_body(const RowArgs& a, const int lb) {
 #pragma unroll
     for (int j = 0; j < E; ++j) {
       const int kx = t + j * TPT;
-      v[j] = valid ? X[xbase + (int64_t)(kx / CB) * kbstride + (kx % CB)] : cx<T>{T(0), T(0)};
+      v[j] = valid ? gld<T>(X, xbase + (int64_t)(kx / CB) * kbstride + (kx % CB)) : cx<T>{T(0), T(0)};
     }
     if constexpr (TWR) fft_cached<T, M, E, true, SPLIT>(v, shr, twc, t);
     else fft<T, M, E, true, SPLIT>(v, shr, tw, t);
-    cx<T>* p = (cx<T>*)a.p;
-    const cx<T>* Vp = (const cx<T>*)a.V;
+    void* p = a.p;
+    const void* Vp = a.V;
 #pragma unroll
     for (int j = 0; j < E; ++j) {
       const int x = t + j * TPT;
@@ -254,56 +254,54 @@ __device__ __forceinline__ void row_pass_body(const RowArgs& a, const int lb) {
       if (j < E / 2 && valid && x < a.nx) {
         const int64_t i = sp_base + x;
         const cx<T> u = v[j];
-        if (a.ustore) ((cx<T>*)a.ustore)[i] = u;
+        if (a.ustore) gst<T>(a.ustore, i, u);
         if (a.acc == ACC_INIT) {
-          p[i] = u;
-          if (a.pstore) ((cx<T>*)a.pstore)[i] = u;
-          if constexpr (sizeof(T) == 4) ((uint32_t*)a.c)[i] = 0u;
+          gst<T>(p, i, u);
+          if (a.pstore) gst<T>(a.pstore, i, u);
+          if constexpr (sizeof(T) == 4) gst1<uint32_t>(a.c, i, 0u);
           const double n = norm2(u);
           su += n;
           sp += n;
         } else if (a.acc == ACC_ADD) {
-          cx<T> pp = p[i];
+          cx<T> pp = gld<T>(p, i);
           if constexpr (sizeof(T) == 4) {
-            uint32_t* cc = (uint32_t*)a.c;
             cx<T> ci;
-            bf16_unpack(cc[i], ci.x, ci.y);
+            bf16_unpack(gld1<uint32_t>(a.c, i), ci.x, ci.y);
             kahan_add(pp.x, ci.x, u.x);
             kahan_add(pp.y, ci.y, u.y);
-            cc[i] = bf16_pack(ci.x, ci.y);
+            gst1<uint32_t>(a.c, i, bf16_pack(ci.x, ci.y));
           } else {
             pp = pp + u;
           }
-          p[i] = pp;
-          if (a.pstore) ((cx<T>*)a.pstore)[i] = pp;
+          gst<T>(p, i, pp);
+          if (a.pstore) gst<T>(a.pstore, i, pp);
           su += norm2(u);
           sp += norm2(pp);
         } else if (a.acc == ACC_PAIR) {
-          cx<T>* g = (cx<T>*)a.grad;
-          const cx<T> pr = ((const cx<T>*)a.pair)[i];
-          g[i] = g[i] + cmulc(pr, u);   // conj(u) * P
+          const cx<T> pr = gld<T>(a.pair, i);
+          gst<T>(a.grad, i, gld<T>(a.grad, i) + cmulc(pr, u));   // conj(u) * P
           su += norm2(u);
         }
         if (a.out_spec && Vp != nullptr) {
-          const cx<T> vv = Vp[srow + x];
+          const cx<T> vv = gld<T>(Vp, srow + x);
           w = a.conj_v ? cmulc(u, vv) : cmul(u, vv);
         }
       }
       v[j] = w;
     }
   } else {
-    const cx<T>* src = (const cx<T>*)a.src;
-    const cx<T>* Vp = (const cx<T>*)a.V;
+    const void* src = a.src;
+    const void* Vp = a.V;
 #pragma unroll
     for (int j = 0; j < E; ++j) {
       const int x = t + j * TPT;
       cx<T> w = {T(0), T(0)};
       if (j < E / 2 && valid && x < a.nx) {
-        w = src[sp_base + x];
+        w = gld<T>(src, sp_base + x);
         if (a.in_mode == ROW_IN_SPATIAL) {
           const cx<T> u0 = w;
           if (Vp != nullptr) {
-            const cx<T> vv = Vp[srow + x];
+            const cx<T> vv = gld<T>(Vp, srow + x);
             w = a.conj_v ? cmulc(w, vv) : cmul(w, vv);
           } else {
             w = cx<T>{T(0), T(0)};
@@ -331,8 +329,8 @@ __device__ __forceinline__ void row_pass_body(const RowArgs& a, const int lb) {
         a0 += red[2 * k];
         a1 += red[2 * k + 1];
       }
-      a.partials[2 * ((int64_t)rhs * nblk + rb)] = a0;
-      a.partials[2 * ((int64_t)rhs * nblk + rb) + 1] = a1;
+      gst1<double>(a.partials, 2 * ((int64_t)rhs * nblk + rb), a0);
+      gst1<double>(a.partials, 2 * ((int64_t)rhs * nblk + rb) + 1, a1);
     }
   }
 
@@ -343,7 +341,7 @@ __device__ __forceinline__ void row_pass_body(const RowArgs& a, const int lb) {
 #pragma unroll
       for (int j = 0; j < E; ++j) {
         const int kx = t + j * TPT;
-        X[xbase + (int64_t)(kx / CB) * kbstride + (kx % CB)] = v[j];
+        gst<T>(X, xbase + (int64_t)(kx / CB) * kbstride + (kx % CB), v[j]);
       }
     }
   }
@@ -376,8 +374,8 @@ __device__ __forceinline__ void col_pass_body(const ColArgs& a, const int lb) {
   const bool cvalid = (i0 * a.zcols + col / a.cb) < a.zlim;
   LdsT* shc = sh + col * LD;
   const cx<T>* tw = (const cx<T>*)a.tw;
-  const cx<T>* in = (const cx<T>*)a.in;
-  cx<T>* out = (cx<T>*)a.out;
+  const void* in = a.in;
+  void* out = a.out;
   // a.sub > 1: the block holds NC of the cb columns of layout block i1 / sub
   const int blk = i1 / a.sub;
   const int c0 = (i1 % a.sub) * NC;
@@ -395,13 +393,13 @@ __device__ __forceinline__ void col_pass_body(const ColArgs& a, const int lb) {
   if (UNIFORM && cvalid && a.n_in >= NLD * TPT) {
 #pragma unroll
     for (int j = 0; j < E; ++j)
-      v[j] = j < NLD ? in[ib + (tt + j * TPT) * a.in_astride] : cx<T>{T(0), T(0)};
+      v[j] = j < NLD ? gld<T>(in, ib + (tt + j * TPT) * a.in_astride) : cx<T>{T(0), T(0)};
   } else {
 #pragma unroll
     for (int j = 0; j < E; ++j) {
       const int pos = tt + j * TPT;
       const bool ld = j < NLD && cvalid && pos < a.n_in;
-      v[j] = ld ? in[ib + pos * a.in_astride] : cx<T>{T(0), T(0)};
+      v[j] = ld ? gld<T>(in, ib + pos * a.in_astride) : cx<T>{T(0), T(0)};
     }
   }
   if constexpr (TWR) tw_load<T, M, E>(twc, tw, tt);
@@ -410,12 +408,12 @@ __device__ __forceinline__ void col_pass_body(const ColArgs& a, const int lb) {
     else fft<T, M, E, false, SPLIT>(v, shc, tw, tt);
   }
   if constexpr (CONV) {
-    const cx<T>* g = (const cx<T>*)a.ghat;
+    const void* g = a.ghat;
     const int kx = blk * a.cb + c0 + (col % a.cb);
     const int64_t gb = fold(kx, a.mx) * a.g_sx + fold(i0, a.mm) * a.g_sm;
 #pragma unroll
     for (int j = 0; j < E; ++j) {
-      const cx<T> gv = g[gb + fold(tt + j * TPT, M)];
+      const cx<T> gv = gld<T>(g, gb + fold(tt + j * TPT, M));
       v[j] = a.conj_g ? cmulc(v[j], gv) : cmul(v[j], gv);
     }
   }
@@ -426,12 +424,12 @@ __device__ __forceinline__ void col_pass_body(const ColArgs& a, const int lb) {
   constexpr int NST = HALF_OUT ? E / 2 : E;  // registers that can hold output
   if (UNIFORM && cvalid && a.n_out >= NST * TPT) {
 #pragma unroll
-    for (int j = 0; j < NST; ++j) out[ob + (tt + j * TPT) * a.out_astride] = v[j];
+    for (int j = 0; j < NST; ++j) gst<T>(out, ob + (tt + j * TPT) * a.out_astride, v[j]);
   } else if (cvalid) {
 #pragma unroll
     for (int j = 0; j < NST; ++j) {
       const int pos = tt + j * TPT;
-      if (pos < a.n_out) out[ob + pos * a.out_astride] = v[j];
+      if (pos < a.n_out) gst<T>(out, ob + pos * a.out_astride, v[j]);
     }
   }
 }
