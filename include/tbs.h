@@ -182,6 +182,22 @@ int tbs_potential(tbs_plan *plan, const double *c_dev, double omega, double c0, 
 int tbs_solve(tbs_plan *plan, const void *source, const void *potential, int nterms,
               void *p_out, double *residual_out);
 
+/* tbs_solve for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, results (bitwise) and errors as tbs_solve, but the series'
+ * workspace (x-spectral intermediate, 3D y intermediate, Kahan compensation,
+ * norm partials, residuals) lives in a static device array of the library,
+ * 128 MiB per GPU, held from the first call on a device until the process
+ * ends; no device memory is allocated or freed.  Plans whose workspace
+ * exceeds it (e.g. 2048^2 FP32 with B >= 2: B (M_x N_y 8 + P 4) bytes plus
+ * partials) return TBS_ERR_UNSUPPORTED, as do density-contrast plans.  The
+ * array keeps the last call's contents; every region is overwritten before it
+ * is read.  All calls on one GPU share that GPU's array: calls that overlap
+ * in time on one device (concurrent streams, threads or processes) race and
+ * give undefined results. */
+int tbs_solve_noalloc(tbs_plan *plan, const void *source, const void *potential, int nterms,
+                      void *p_out, double *residual_out);
+
 /* Second-harmonic source S2 = -(1/2) xi (2 omega)^2 p1^2, xi = (1 + B/2A) /
  * (rho c^4) with the local sound speed c (Sec. 2.1.4 Eq. nonlinear_waveeqn_shi2,
  * Sec. 2.3.4 Eq. TBS_solution_shi_2, sum term only).

@@ -37,7 +37,7 @@ EXPORTS = (
     "tbs_last_error", "tbs_batch_create", "tbs_batch_solve", "tbs_batch_destroy",
     "tbs_batch_last_error", "tbs_plan_autotune", "tbs_green_periodic", "tbs_abl_profile",
     "tbs_kspace_coefficients", "tbs_density_contrast",
-    "tbs_iterate", "tbs_batch_profile_enable", "tbs_batch_profile_read",
+    "tbs_iterate", "tbs_batch_profile_enable", "tbs_batch_profile_read", "tbs_solve_noalloc",
 )
 PASS_KINDS = ("row_first", "row_mid", "row_last", "col_conv", "col_fwd", "col_inv")
 
@@ -87,6 +87,7 @@ def library() -> ctypes.CDLL:
         "tbs_green_export": (ctypes.c_int, [vp, vp]),
         "tbs_potential": (ctypes.c_int, [vp, vp] + [ctypes.c_double] * 5 + [vp, vp]),
         "tbs_solve": (ctypes.c_int, [vp, vp, vp, ctypes.c_int, vp, dp]),
+        "tbs_solve_noalloc": (ctypes.c_int, [vp, vp, vp, ctypes.c_int, vp, dp]),
         "tbs_harmonic_source_n": (ctypes.c_int, [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_void_p), vp,
                                                   ctypes.c_double, ctypes.c_double, ctypes.c_double, vp]),
         "tbs_harmonic_source": (ctypes.c_int, [vp, vp, vp, ctypes.c_double, ctypes.c_double,
@@ -342,6 +343,20 @@ class Plan:
         rc = library().tbs_solve(self._h, sp, vp, int(nterms), op,
                                  res.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if residual else None)
         _check(rc, self._h, "tbs_solve")
+        return (out, res) if residual else out
+
+    def solve_noalloc(self, source, potential, nterms: int, out, residual: bool = False):
+        """solve() on the library's static workspace (tbs_solve_noalloc): no
+        device allocation by the library or here, so `out` is required."""
+        torch = _torch()
+        sp = _ptr(source, self.dtype, self._bshape(), "source")
+        vp = _ptr(potential, self.dtype, self.shape, "potential")
+        op = _ptr(out, self.dtype, self._bshape(), "out")
+        res = np.empty((self.batch, nterms), dtype=np.float64) if residual else None
+        self._sync_stream()
+        rc = library().tbs_solve_noalloc(self._h, sp, vp, int(nterms), op,
+                                         res.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if residual else None)
+        _check(rc, self._h, "tbs_solve_noalloc")
         return (out, res) if residual else out
 
     def harmonic_source(self, p1, c, omega: float, rho: float, BA: float, out=None):

@@ -513,6 +513,48 @@ int check_plan_ready(tbs_plan* p) {
 
 }  // namespace
 
+// ------------------------------------------------------- static workspace --
+// tbs_solve_noalloc keeps the series' workspace in this file-scope device
+// array: one copy per GPU, held until the process ends.  In host code the
+// array's name only stands in for the device symbol; its device address is
+// taken once per device with hipGetSymbolAddress and used from then on.
+#define TBS_SCRATCH_BYTES (128ull << 20)
+static __device__ __align__(256) unsigned char scratch[TBS_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the scratch array on the plan's device (looked up on the
+// first call for that device, with that device current).
+int scratch_address(tbs_plan* p, void** out) {
+  if (p->device < 0 || p->device >= kMaxDevices)
+    return fail(p, TBS_ERR_UNSUPPORTED, "device index beyond the static workspace table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[p->device]) {
+    int cur = 0;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return hip_fail(p, e, "hipGetDevice");
+    if (cur != p->device && (e = hipSetDevice(p->device)) != hipSuccess) return hip_fail(p, e, "hipSetDevice");
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != p->device) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return hip_fail(p, e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+    }
+    g_scratch_ptr[p->device] = ptr;
+  }
+  *out = g_scratch_ptr[p->device];
+  return TBS_OK;
+}
+
+size_t align256(size_t n) { return (n + 255) / 256 * 256; }
+
+}  // namespace
+
 // ------------------------------------------------------------- batches ----
 
 struct tbs_batch {
@@ -1242,6 +1284,68 @@ int tbs_solve(tbs_plan* p, const void* source, const void* V, int nterms, void* 
   if (rc) return rc;
   if (residual_out) return check_residuals(p, residual_out, nterms);
   return TBS_OK;
+}
+
+int tbs_solve_noalloc(tbs_plan* p, const void* source, const void* V, int nterms, void* p_out,
+                      double* residual_out) {
+  int rc = check_plan_ready(p);
+  if (rc) return rc;
+  if (!source || !p_out) return fail(p, TBS_ERR_INVALID, "source and p_out are required");
+  if (nterms < 1 || nterms > 100000) return fail(p, TBS_ERR_INVALID, "nterms must be >= 1");
+  if (p_out == source || p_out == V) return fail(p, TBS_ERR_INVALID, "p_out aliases an input");
+  if (p->gamma)
+    return fail(p, TBS_ERR_UNSUPPORTED, "density-contrast plans keep a spatial term buffer: use tbs_solve");
+  // workspace layout in the scratch array: X | 3D y intermediate | Kahan
+  // compensation | norm partials | residuals (each 256-byte aligned); every
+  // region is written before it is read, so nothing needs clearing
+  const size_t B = (size_t)p->batch;
+  const size_t L = (size_t)nterms;
+  const size_t x_bytes = align256(p->X_bytes);
+  const size_t y_bytes = p->ndim == 3 ? align256(B * p->M[0] * p->M[1] * p->N[2] * p->esz) : 0;
+  const size_t c_bytes = p->kc ? align256(p->kc_bytes) : 0;
+  const size_t part_n = (size_t)2 * B * row_blocks(p) * L;
+  const size_t part_bytes = align256(part_n * sizeof(double));
+  const size_t res_bytes = align256(B * L * sizeof(double));
+  const size_t need = x_bytes + y_bytes + c_bytes + part_bytes + res_bytes;
+  if (need > TBS_SCRATCH_BYTES)
+    return fail(p, TBS_ERR_UNSUPPORTED,
+                "tbs_solve_noalloc: the workspace of " + std::to_string(need) +
+                    " bytes exceeds the static scratch of " + std::to_string(TBS_SCRATCH_BYTES) +
+                    " bytes (use tbs_solve)");
+  void* base = nullptr;
+  rc = scratch_address(p, &base);
+  if (rc) return rc;
+  char* w = (char*)base;
+  // run the plan's series on the scratch regions, then restore its own buffers
+  void* const sv_X = p->X;
+  void* const sv_xcur = p->xcur;
+  void* const sv_Yb = p->Yb;
+  void* const sv_kc = p->kc;
+  double* const sv_part = p->partials;
+  const size_t sv_part_cap = p->partials_cap;
+  double* const sv_res = p->resid;
+  const size_t sv_res_cap = p->resid_cap;
+  const bool sv_prof = p->prof;
+  p->X = p->xcur = w;
+  if (y_bytes) p->Yb = w + x_bytes;
+  if (c_bytes) p->kc = w + x_bytes + y_bytes;
+  p->partials = (double*)(w + x_bytes + y_bytes + c_bytes);
+  p->partials_cap = part_n;
+  p->resid = (double*)(w + x_bytes + y_bytes + c_bytes + part_bytes);
+  p->resid_cap = B * L;
+  p->prof = false;  // profiling events are created on demand
+  rc = forward_series(p, source, V, nterms, p_out, nullptr);
+  if (!rc && residual_out) rc = check_residuals(p, residual_out, nterms);
+  p->X = sv_X;
+  p->xcur = sv_xcur;
+  p->Yb = sv_Yb;
+  p->kc = sv_kc;
+  p->partials = sv_part;
+  p->partials_cap = sv_part_cap;
+  p->resid = sv_res;
+  p->resid_cap = sv_res_cap;
+  p->prof = sv_prof;
+  return rc;
 }
 
 int tbs_harmonic_source(tbs_plan* p, const void* p1, const double* c, double omega, double rho,
