@@ -221,6 +221,22 @@ int tbs_harmonic_source(tbs_plan *plan, const void *p1_dev, const double *c_dev,
 int tbs_harmonic_source_n(tbs_plan *plan, int n, const void *const *fields_dev, const double *c_dev,
                           double omega, double rho, double BA, void *S_dev);
 
+/* The n-th harmonic source of tbs_harmonic_source_n on scaled fields, for
+ * chains whose higher harmonics fall below the FP32 range (in the paper's
+ * 4096^2 setup the 5th harmonic is about 1e-39; Sec. 3.1, Table 3).  Field a
+ * (a = 1 .. n-1) holds psi_a * 2^field_exp[a-1] (host int [n-1], |e| <= 900);
+ * the products and sums run in FP64 on the unscaled values, and S_out
+ * receives S_n * 2^e with e (*exp_out) chosen so that the largest real or
+ * imaginary part of S_n * 2^e lies in [1, 2) (e = 0 for S_n = 0).  Because
+ * each solve is linear in its source, the series or iteration driven by
+ * S_out returns psi_n * 2^e: the caller passes e as field n's exponent to the
+ * next order.  Two passes over the fields (maximum, then the scaled values)
+ * and one device-to-host copy of the maximum (synchronises the plan's stream).
+ * Returns TBS_ERR_INVALID for a non-finite source. */
+int tbs_harmonic_source_scaled(tbs_plan *plan, int n, const void *const *fields, const int *field_exp,
+                               const double *c_dev, double omega, double rho, double BA, void *S_out,
+                               int *exp_out);
+
 /* Attach a density contrast to a 2D padded plan (NULL detaches): the term
  * div(gamma grad psi) of the inhomogeneous wave equation (Sec. 2.1.3, Eqs.
  * acoustic_waveequn_time_dependent_inhomogeneous and mismatch_parameters,
@@ -332,10 +348,10 @@ typedef struct tbs_batch tbs_batch;
  * grid, k0 and B right-hand sides) for joint solves.  All plans must be 2D,
  * share the dtype and be tabulated; the batch queues its work on the first
  * plan's stream.  The plans must outlive the batch.  Passes of grids whose
- * padded lengths coincide run in one grouped kernel launch per term.  With two
- * or more plans the work is split in two halves of equal size whose pass
- * sequences run on two streams, one pass apart (environment variable
- * TBS_BATCH_CHAINS=1 keeps a single sequence); results are bitwise the same. */
+ * padded lengths coincide run in one grouped kernel launch per term.  With
+ * the environment variable TBS_BATCH_CHAINS=2 (and two or more plans) the work
+ * is split in two halves of equal size whose pass sequences run on two
+ * streams, one pass apart; results are bitwise the same. */
 int tbs_batch_create(tbs_batch **out, tbs_plan *const *plans, int nplans);
 
 /* The L-term series of every plan in the batch (the tbs_solve contract per

@@ -38,6 +38,7 @@ EXPORTS = (
     "tbs_batch_last_error", "tbs_plan_autotune", "tbs_green_periodic", "tbs_abl_profile",
     "tbs_kspace_coefficients", "tbs_density_contrast",
     "tbs_iterate", "tbs_batch_profile_enable", "tbs_batch_profile_read", "tbs_solve_noalloc",
+    "tbs_harmonic_source_scaled",
 )
 PASS_KINDS = ("row_first", "row_mid", "row_last", "col_conv", "col_fwd", "col_inv")
 
@@ -92,6 +93,10 @@ def library() -> ctypes.CDLL:
                                                   ctypes.c_double, ctypes.c_double, ctypes.c_double, vp]),
         "tbs_harmonic_source": (ctypes.c_int, [vp, vp, vp, ctypes.c_double, ctypes.c_double,
                                                ctypes.c_double, vp]),
+        "tbs_harmonic_source_scaled": (ctypes.c_int, [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_void_p),
+                                                      ctypes.POINTER(ctypes.c_int), vp, ctypes.c_double,
+                                                      ctypes.c_double, ctypes.c_double, vp,
+                                                      ctypes.POINTER(ctypes.c_int)]),
         "tbs_adjoint": (ctypes.c_int, [vp, vp, vp, ctypes.c_int, vp, vp, dp, ctypes.c_int]),
         "tbs_misfit": (ctypes.c_int, [vp, vp, vp, ctypes.c_int, vp, vp, vp]),
         "tbs_speed_gradient": (ctypes.c_int, [vp, vp, vp, vp, ctypes.c_int]),
@@ -386,6 +391,25 @@ class Plan:
         _check(library().tbs_harmonic_source_n(self._h, int(n), ptrs, cp, omega, rho, BA, op), self._h,
                "tbs_harmonic_source_n")
         return out
+
+    def harmonic_source_scaled(self, n: int, fields, exps, c, omega: float, rho: float, BA: float, out=None):
+        """S_n * 2^e from fields psi_a * 2^exps[a-1] (a = 1 .. n-1); returns
+        (S_out, e).  The solve driven by S_out yields psi_n * 2^e."""
+        torch = _torch()
+        if len(fields) < n - 1 or len(exps) < n - 1:
+            raise ValueError("harmonic_source_scaled needs psi_1 .. psi_{n-1} and their exponents")
+        ptrs = (ctypes.c_void_p * max(1, n - 1))(*[_ptr(f, self.dtype, self._bshape(), "field")
+                                                   for f in fields[: n - 1]])
+        ex = (ctypes.c_int * max(1, n - 1))(*[int(e) for e in exps[: n - 1]])
+        cp = _ptr(c, torch.float64, self.shape, "c")
+        if out is None:
+            out = torch.empty(self._bshape(), dtype=self.dtype, device=fields[0].device)
+        op = _ptr(out, self.dtype, self._bshape(), "out")
+        e = ctypes.c_int()
+        self._sync_stream()
+        _check(library().tbs_harmonic_source_scaled(self._h, int(n), ptrs, ex, cp, omega, rho, BA, op,
+                                                    ctypes.byref(e)), self._h, "tbs_harmonic_source_scaled")
+        return out, e.value
 
     def density_contrast(self, gamma=None):
         """Attach (float64 device map, shape of the grid) or detach (None) the

@@ -22,7 +22,7 @@
 using tbs::zd;
 
 #ifndef TBS_BATCH_CHAINS_DEFAULT
-#define TBS_BATCH_CHAINS_DEFAULT 2
+#define TBS_BATCH_CHAINS_DEFAULT 1
 #endif
 
 struct tbs_plan {
@@ -1366,8 +1366,39 @@ int tbs_harmonic_source_n(tbs_plan* p, int n, const void* const* fields, const d
   if (!(omega > 0) || !(rho > 0) || !is_fin(BA)) return fail(p, TBS_ERR_INVALID, "bad parameters");
   const double nw = (double)n * omega;
   const double coef = -0.5 * (1.0 + 0.5 * BA) / rho * nw * nw;
-  TBS_LAUNCH(p, tbs::launch_harmonic_source_n(n, fields, c, S, p->fp64, p->P, p->batch, coef,
-                                              p->stream));
+  TBS_LAUNCH(p, tbs::launch_harmonic_source_n(n, fields, nullptr, c, S, p->fp64, p->P, p->batch, coef,
+                                              1.0, p->stream));
+  return TBS_OK;
+}
+
+int tbs_harmonic_source_scaled(tbs_plan* p, int n, const void* const* fields, const int* field_exp,
+                               const double* c, double omega, double rho, double BA, void* S,
+                               int* exp_out) {
+  if (!p || !fields || !field_exp || !c || !S || !exp_out) return fail(p, TBS_ERR_INVALID, "NULL argument");
+  if (n < 2 || n > TBS_HARMONIC_MAX) return fail(p, TBS_ERR_INVALID, "harmonic order must be 2..9");
+  double unscale[TBS_HARMONIC_MAX - 1];
+  for (int a = 0; a < n - 1; ++a) {
+    if (!fields[a]) return fail(p, TBS_ERR_INVALID, "NULL lower-harmonic field");
+    if (field_exp[a] < -900 || field_exp[a] > 900) return fail(p, TBS_ERR_INVALID, "field exponent out of range");
+    unscale[a] = std::ldexp(1.0, -field_exp[a]);
+  }
+  if (!(omega > 0) || !(rho > 0) || !is_fin(BA)) return fail(p, TBS_ERR_INVALID, "bad parameters");
+  const double nw = (double)n * omega;
+  const double coef = -0.5 * (1.0 + 0.5 * BA) / rho * nw * nw;
+  int rc = ensure_doubles(p, &p->jpart, &p->jpart_cap, (size_t)tbs::kHarmonicMaxSlots);
+  if (rc) return rc;
+  TBS_LAUNCH(p, tbs::launch_harmonic_source_n_max(n, fields, unscale, c, p->fp64, p->P, p->batch, coef,
+                                                  p->jpart, p->stream));
+  double mx = 0.0;
+  TBS_HIP(p, hipMemcpyAsync(&mx, p->jpart + (tbs::kHarmonicMaxSlots - 1), sizeof(double),
+                            hipMemcpyDeviceToHost, p->stream));
+  TBS_HIP(p, hipStreamSynchronize(p->stream));
+  if (!is_fin(mx)) return fail(p, TBS_ERR_INVALID, "non-finite harmonic source (non-finite fields?)");
+  // 2^e brings the largest component into [1, 2)
+  const int e = mx > 0.0 ? -std::ilogb(mx) : 0;
+  TBS_LAUNCH(p, tbs::launch_harmonic_source_n(n, fields, unscale, c, S, p->fp64, p->P, p->batch, coef,
+                                              std::ldexp(1.0, e), p->stream));
+  *exp_out = e;
   return TBS_OK;
 }
 
@@ -1630,7 +1661,7 @@ int tbs_batch_create(tbs_batch** out, tbs_plan* const* plans, int nplans) {
     tbs_batch_destroy(b);
     return fail(nullptr, TBS_ERR_HIP, "batch stream/events");
   }
-  // two chains for batches of several plans (TBS_BATCH_CHAINS=1 keeps one)
+  // one launch chain, or two for batches of several plans (TBS_BATCH_CHAINS=2)
   b->chains = nplans >= 2 ? TBS_BATCH_CHAINS_DEFAULT : 1;
   if (const char* env = std::getenv("TBS_BATCH_CHAINS")) b->chains = (std::atoi(env) == 2 && nplans >= 2) ? 2 : 1;
   if (b->chains == 2 &&

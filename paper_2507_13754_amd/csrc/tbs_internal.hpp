@@ -165,8 +165,17 @@ int launch_harmonic_source(const void* p1, const double* c, void* S2, bool fp64,
                            int nrhs, double coef, hipStream_t s);
 // highest harmonic order accepted by launch_harmonic_source_n
 #define TBS_HARMONIC_MAX 9
-int launch_harmonic_source_n(int n, const void* const* fields, const double* c, void* S, bool fp64,
-                             int64_t np, int nrhs, double coef, hipStream_t s);
+// unscale: NULL or host double [n-1] (field a holds psi_a / unscale[a-1]);
+// the output is multiplied by out_scale
+int launch_harmonic_source_n(int n, const void* const* fields, const double* unscale, const double* c,
+                             void* S, bool fp64, int64_t np, int nrhs, double coef, double out_scale,
+                             hipStream_t s);
+// max |Re|, |Im| of the unscaled S_n into partial[1024] (partial: dev double
+// [1025]; partial[0..1023] are block maxima)
+int launch_harmonic_source_n_max(int n, const void* const* fields, const double* unscale, const double* c,
+                                 bool fp64, int64_t np, int nrhs, double coef, double* partial,
+                                 hipStream_t s);
+constexpr int kHarmonicMaxSlots = 1025;
 int launch_misfit(const void* p, const int64_t* rec, const void* p_obs, void* q, double* jpart,
                   bool fp64, int64_t P, int nrec, int nrhs, hipStream_t s);
 int launch_grad_assemble(const void* g, int nrhs, const void* dVdc, double* grad_c, bool fp64,

@@ -188,42 +188,117 @@ int launch_harmonic_source(const void* p1, const double* c, void* S2, bool fp64,
 // nonlinear solutions with sum terms): S_n = coef / c^4 * sum_{a=1}^{n-1}
 // psi_a psi_{n-a} (ordered pairs, so the a = n-a term enters once), with
 // coef = -(1/2)(1 + B/2A)(n omega)^2 / rho; products and sum in FP64.
+// Scaled form: field a holds psi_a 2^{e_a} (unscale[a-1] = 2^{-e_a}) and the
+// output is S_n 2^{e_n} (out_scale = 2^{e_n}); all of it in FP64, so fields
+// far below the FP32 range keep their precision.
 struct HarmonicFields {
   const void* f[TBS_HARMONIC_MAX - 1];
+  double unscale[TBS_HARMONIC_MAX - 1];
 };
 
 template <typename T>
+__device__ __forceinline__ void harmonic_value(const HarmonicFields& h, int n, const double* c, int64_t np,
+                                               int64_t i, double coef, double& re, double& im) {
+  double ar = 0.0, ai = 0.0;
+  for (int a = 1; a <= n / 2; ++a) {
+    const cx<T> x = ((const cx<T>*)h.f[a - 1])[i];
+    const cx<T> y = ((const cx<T>*)h.f[n - a - 1])[i];
+    const double w = ((2 * a == n) ? 1.0 : 2.0) * h.unscale[a - 1] * h.unscale[n - a - 1];
+    ar += w * ((double)x.x * (double)y.x - (double)x.y * (double)y.y);
+    ai += w * ((double)x.x * (double)y.y + (double)x.y * (double)y.x);
+  }
+  const double ci = c[i % np];
+  const double g = coef / (ci * ci * ci * ci);
+  re = g * ar;
+  im = g * ai;
+}
+
+template <typename T>
 __global__ void __launch_bounds__(256) k_harmonic_n(HarmonicFields h, int n, const double* c,
-                                                    cx<T>* S, int64_t np, int nrhs, double coef) {
+                                                    cx<T>* S, int64_t np, int nrhs, double coef,
+                                                    double out_scale) {
   const int64_t tot = np * nrhs;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot;
        i += (int64_t)gridDim.x * blockDim.x) {
-    double ar = 0.0, ai = 0.0;
-    for (int a = 1; a <= n / 2; ++a) {
-      const cx<T> x = ((const cx<T>*)h.f[a - 1])[i];
-      const cx<T> y = ((const cx<T>*)h.f[n - a - 1])[i];
-      const double w = (2 * a == n) ? 1.0 : 2.0;
-      ar += w * ((double)x.x * (double)y.x - (double)x.y * (double)y.y);
-      ai += w * ((double)x.x * (double)y.y + (double)x.y * (double)y.x);
-    }
-    const double ci = c[i % np];
-    const double g = coef / (ci * ci * ci * ci);
-    S[i] = cx<T>{(T)(g * ar), (T)(g * ai)};
+    double re, im;
+    harmonic_value<T>(h, n, c, np, i, coef, re, im);
+    S[i] = cx<T>{(T)(re * out_scale), (T)(im * out_scale)};
   }
 }
 
-int launch_harmonic_source_n(int n, const void* const* fields, const double* c, void* S, bool fp64,
-                             int64_t np, int nrhs, double coef, hipStream_t s) {
+// Largest |S_n| (FP64, unscaled fields as above) per block of a fixed grid
+// (kHarmMaxBlocks blocks), then over the blocks: partial[kHarmMaxBlocks] holds
+// the result.  No atomics: the second kernel is one block.
+constexpr int kHarmMaxBlocks = 1024;
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_harmonic_n_max(HarmonicFields h, int n, const double* c,
+                                                        int64_t np, int nrhs, double coef, double* partial) {
+  __shared__ double red[256];
+  const int64_t tot = np * nrhs;
+  double m = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double re, im;
+    harmonic_value<T>(h, n, c, np, i, coef, re, im);
+    m = fmax(m, fmax(fabs(re), fabs(im)));
+  }
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(256) k_max_blocks(double* partial, int nb) {
+  __shared__ double red[256];
+  double m = 0.0;
+  for (int i = threadIdx.x; i < nb; i += 256) m = fmax(m, partial[i]);
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[nb] = red[0];
+}
+
+int launch_harmonic_source_n(int n, const void* const* fields, const double* unscale, const double* c,
+                             void* S, bool fp64, int64_t np, int nrhs, double coef, double out_scale,
+                             hipStream_t s) {
   HarmonicFields h{};
-  for (int a = 0; a < n - 1; ++a) h.f[a] = fields[a];
+  for (int a = 0; a < n - 1; ++a) {
+    h.f[a] = fields[a];
+    h.unscale[a] = unscale ? unscale[a] : 1.0;
+  }
   const int64_t blocks = (np * nrhs + 255) / 256;
   const dim3 g((unsigned)(blocks < 65536 * 8 ? blocks : 65536 * 8));
   if (fp64)
     hipLaunchKernelGGL(k_harmonic_n<double>, g, dim3(256), 0, s, h, n, c, (cx<double>*)S, np, nrhs,
-                       coef);
+                       coef, out_scale);
   else
     hipLaunchKernelGGL(k_harmonic_n<float>, g, dim3(256), 0, s, h, n, c, (cx<float>*)S, np, nrhs,
-                       coef);
+                       coef, out_scale);
+  return (int)hipGetLastError();
+}
+
+int launch_harmonic_source_n_max(int n, const void* const* fields, const double* unscale, const double* c,
+                                 bool fp64, int64_t np, int nrhs, double coef, double* partial,
+                                 hipStream_t s) {
+  HarmonicFields h{};
+  for (int a = 0; a < n - 1; ++a) {
+    h.f[a] = fields[a];
+    h.unscale[a] = unscale ? unscale[a] : 1.0;
+  }
+  if (fp64)
+    hipLaunchKernelGGL(k_harmonic_n_max<double>, dim3(kHarmMaxBlocks), dim3(256), 0, s, h, n, c, np, nrhs,
+                       coef, partial);
+  else
+    hipLaunchKernelGGL(k_harmonic_n_max<float>, dim3(kHarmMaxBlocks), dim3(256), 0, s, h, n, c, np, nrhs,
+                       coef, partial);
+  hipLaunchKernelGGL(k_max_blocks, dim3(1), dim3(256), 0, s, partial, kHarmMaxBlocks);
   return (int)hipGetLastError();
 }
 

@@ -57,6 +57,12 @@
 #ifndef TBS_OCC_HINT
 #define TBS_OCC_HINT 1      // size each pass's register budget to its LDS occupancy
 #endif
+#ifndef TBS_PREFETCH
+#define TBS_PREFETCH 0      // loads issued with the line's own: 1 row sum + compensation,
+#endif                      // 2 row potential, 4 column spectrum
+#define TBS_PF_ACC ((TBS_PREFETCH & 1) != 0)
+#define TBS_PF_V ((TBS_PREFETCH & 2) != 0)
+#define TBS_PF_G ((TBS_PREFETCH & 4) != 0)
 
 namespace tbs {
 
@@ -160,7 +166,13 @@ template <typename T>
 constexpr int tw_resident_vgprs(int M, int E, bool row) {
   const bool odd = (M & (M - 1)) != 0;
   const int rest = odd ? (row ? 72 : 80) : (row ? (M <= 512 ? 48 : 40) : 32);
-  return (int)(sizeof(T) / 2) * (E + tw_cache_size(M, E)) + rest * (int)(sizeof(T) / 4);
+  // early-issued loads held in registers across the first transform: per
+  // value of the first half of the line the sum, its compensation and the
+  // potential (row pass; 5 VGPRs in FP32, 8 in FP64), or per value the
+  // spectrum (column pass)
+  const int pre = row ? (E / 2) * ((TBS_PF_ACC ? (sizeof(T) == 4 ? 3 : 4) : 0) + (TBS_PF_V ? (int)(sizeof(T) / 2) : 0))
+                      : (TBS_PF_G ? E * (int)(sizeof(T) / 2) : 0);
+  return (int)(sizeof(T) / 2) * (E + tw_cache_size(M, E)) + rest * (int)(sizeof(T) / 4) + pre;
 }
 template <typename T>
 constexpr bool tw_resident(int M, int E, int lines, bool split, bool row) {
@@ -243,10 +255,35 @@ __device__ __forceinline__ void row_pass_body(const RowArgs& a, const int lb) {
       const int kx = t + j * TPT;
       v[j] = valid ? gld<T>(X, xbase + (int64_t)(kx / CB) * kbstride + (kx % CB)) : cx<T>{T(0), T(0)};
     }
-    if constexpr (TWR) fft_cached<T, M, E, true, SPLIT>(v, shr, twc, t);
-    else fft<T, M, E, true, SPLIT>(v, shr, tw, t);
     void* p = a.p;
     const void* Vp = a.V;
+    // The sum, its compensation and the potential of this row do not depend
+    // on the transform: their loads can be issued with the spectrum's, so
+    // that their latency overlaps the inverse FFT (TBS_PREFETCH).
+    constexpr int EA = TBS_PF_ACC ? E / 2 : 1;
+    constexpr int EV = TBS_PF_V ? E / 2 : 1;
+    cx<T> pre_p[EA], pre_v[EV];
+    uint32_t pre_c[EA];
+    if constexpr (TBS_PF_ACC) {
+      const bool pf = a.acc == ACC_ADD;
+#pragma unroll
+      for (int j = 0; j < EA; ++j) {
+        const int x = t + j * TPT;
+        const bool in = pf && valid && x < a.nx;
+        pre_p[j] = in ? gld<T>(p, sp_base + x) : cx<T>{T(0), T(0)};
+        pre_c[j] = (sizeof(T) == 4 && in) ? gld1<uint32_t>(a.c, sp_base + x) : 0u;
+      }
+    }
+    if constexpr (TBS_PF_V) {
+      const bool pf = a.out_spec && Vp != nullptr;
+#pragma unroll
+      for (int j = 0; j < EV; ++j) {
+        const int x = t + j * TPT;
+        pre_v[j] = (pf && valid && x < a.nx) ? gld<T>(Vp, srow + x) : cx<T>{T(0), T(0)};
+      }
+    }
+    if constexpr (TWR) fft_cached<T, M, E, true, SPLIT>(v, shr, twc, t);
+    else fft<T, M, E, true, SPLIT>(v, shr, tw, t);
 #pragma unroll
     for (int j = 0; j < E; ++j) {
       const int x = t + j * TPT;
@@ -263,10 +300,10 @@ __device__ __forceinline__ void row_pass_body(const RowArgs& a, const int lb) {
           su += n;
           sp += n;
         } else if (a.acc == ACC_ADD) {
-          cx<T> pp = gld<T>(p, i);
+          cx<T> pp = TBS_PF_ACC ? pre_p[j % EA] : gld<T>(p, i);
           if constexpr (sizeof(T) == 4) {
             cx<T> ci;
-            bf16_unpack(gld1<uint32_t>(a.c, i), ci.x, ci.y);
+            bf16_unpack(TBS_PF_ACC ? pre_c[j % EA] : gld1<uint32_t>(a.c, i), ci.x, ci.y);
             kahan_add(pp.x, ci.x, u.x);
             kahan_add(pp.y, ci.y, u.y);
             gst1<uint32_t>(a.c, i, bf16_pack(ci.x, ci.y));
@@ -283,7 +320,7 @@ __device__ __forceinline__ void row_pass_body(const RowArgs& a, const int lb) {
           su += norm2(u);
         }
         if (a.out_spec && Vp != nullptr) {
-          const cx<T> vv = gld<T>(Vp, srow + x);
+          const cx<T> vv = TBS_PF_V ? pre_v[j % EV] : gld<T>(Vp, srow + x);
           w = a.conj_v ? cmulc(u, vv) : cmul(u, vv);
         }
       }
@@ -403,17 +440,27 @@ __device__ __forceinline__ void col_pass_body(const ColArgs& a, const int lb) {
     }
   }
   if constexpr (TWR) tw_load<T, M, E>(twc, tw, tt);
+  // the spectrum values of this line, loaded with the line (TBS_PREFETCH) so
+  // that their latency overlaps the forward FFT
+  constexpr int EG = (CONV && TBS_PF_G) ? E : 1;
+  cx<T> pre_g[EG];
+  int64_t gb = 0;
+  if constexpr (CONV) {
+    const int kx = blk * a.cb + c0 + (col % a.cb);
+    gb = fold(kx, a.mx) * a.g_sx + fold(i0, a.mm) * a.g_sm;
+    if constexpr (TBS_PF_G) {
+#pragma unroll
+      for (int j = 0; j < E; ++j) pre_g[j] = gld<T>(a.ghat, gb + fold(tt + j * TPT, M));
+    }
+  }
   if constexpr (OP != COL_INV) {
     if constexpr (TWR) fft_cached<T, M, E, false, SPLIT>(v, shc, twc, tt);
     else fft<T, M, E, false, SPLIT>(v, shc, tw, tt);
   }
   if constexpr (CONV) {
-    const void* g = a.ghat;
-    const int kx = blk * a.cb + c0 + (col % a.cb);
-    const int64_t gb = fold(kx, a.mx) * a.g_sx + fold(i0, a.mm) * a.g_sm;
 #pragma unroll
     for (int j = 0; j < E; ++j) {
-      const cx<T> gv = gld<T>(g, gb + fold(tt + j * TPT, M));
+      const cx<T> gv = TBS_PF_G ? pre_g[j % EG] : gld<T>(a.ghat, gb + fold(tt + j * TPT, M));
       v[j] = a.conj_g ? cmulc(v[j], gv) : cmul(v[j], gv);
     }
   }

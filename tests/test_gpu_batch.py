@@ -132,3 +132,25 @@ def test_batch_rerecords_after_member_plan_grows(dev):
     plans[1].autotune()          # allowed again once the batch is gone
     for p in plans:
         p.close()
+
+
+def test_two_launch_chains_are_bitwise_one(dev, monkeypatch):
+    """TBS_BATCH_CHAINS=2 (two streams, one pass apart) against the default
+    single chain: the same kernels on the same data, bitwise."""
+    import paper_2507_13754_amd as tbs
+    cs = cases(nangles=2, nterms=6)
+    plans, srcs, pots = build(dev, cs, "c64")
+    one = tbs.Batch(plans)
+    ref = [o.clone() for o in one.solve(srcs, pots, 6)]
+    one.close()
+    monkeypatch.setenv("TBS_BATCH_CHAINS", "2")
+    two = tbs.Batch(plans)
+    outs, res = two.solve(srcs, pots, 6, residual=True)
+    for a, b in zip(ref, outs):
+        assert torch.equal(a, b)
+    outs2 = two.solve(srcs, pots, 6, outs=outs)
+    for a, b in zip(ref, outs2):
+        assert torch.equal(a, b)
+    two.close()
+    for p in plans:
+        p.close()

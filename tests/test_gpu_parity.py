@@ -133,6 +133,74 @@ def test_long_slowly_converging_series(dev, dt):
     assert per_rhs_rel(p, p_ref) <= TOL[dt]
 
 
+def _bf16(x):
+    """Round-to-nearest-even of float32 values to bfloat16 (as float32)."""
+    b = np.asarray(x, np.float32).view(np.uint32).astype(np.uint64)
+    r = ((b + 0x7FFF + ((b >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32)
+
+
+def test_compensated_sum_beats_plain_fp32(dev):
+    """An 8000-term series whose terms stay near 1e-4 of the running sum (in
+    norm): one potential cell V(x0) = v at a spot the first term barely
+    reaches, so GV is rank one with eigenvalue v W(0) = 0.99995 e^{2i} and
+    u_n = lambda^{n-1} u_1.  The spectrum is the oracle's rounded to FP32
+    values (imported on both sides) and v an FP32 value, so device and oracle
+    apply the same operator.  The device's sum of terms 1..L-1 (p_L - p_1 on
+    the device) must match the oracle's to 5e-8 of |p|; the same FP32 terms
+    summed without compensation (host emulation) miss it by more than 2e-7,
+    with the compensation stored as bfloat16 (host emulation) by less than
+    5e-8."""
+    import paper_2507_13754_amd as tbs
+    n, L = 48, 8000
+    dx = 1.0
+    k0 = 2 * np.pi / 8 + 0.15j
+    G = oracle.GreenOperator(k0, dx, (n, n))
+    M = G.mshape[0]
+    q = (G.ghat / (M * M)).astype(np.complex64).astype(np.complex128)
+    f = np.minimum(np.arange(M), M - np.arange(M))
+    full = q[f][:, f] * (M * M)             # even, FP32-representable after / M^2
+    G.ghat = full
+    xs, x0 = (6, 6), (40, 40)
+    d0 = np.zeros((n, n), complex)
+    d0[x0] = 1.0
+    W0 = G(d0)[x0]
+    v = complex(np.complex64(0.99995 * np.exp(2.0j) / W0))
+    V = np.zeros((n, n), complex)
+    V[x0] = v
+    s = np.zeros((1, n, n), complex)
+    s[(0,) + xs] = 1.0
+    terms = [G(s)[0]]
+    for _ in range(L - 1):
+        terms.append(G(V * terms[-1]))
+    tail = np.sum(terms[1:], axis=0)        # sum of u_1 .. u_{L-1}, FP64
+    assert 3e-5 < np.linalg.norm(terms[1]) / np.linalg.norm(terms[0]) < 3e-4
+    p1, _ = gpu_solve(dev, (n, n), dx, k0, s, V, 1, "c64", spectrum=full)
+    pL, _ = gpu_solve(dev, (n, n), dx, k0, s, V, L, "c64", spectrum=full)
+    ref = p1[0] + tail
+    dev_err = rel(pL[0], ref)
+    # host emulation of the FP32 summation of the FP32-rounded terms
+    plain = p1[0].astype(np.complex64)
+    sr, si = plain.real.copy(), plain.imag.copy()
+    cr, ci = np.zeros_like(sr), np.zeros_like(si)
+    for t in terms[1:]:
+        t32 = t.astype(np.complex64)
+        plain = (plain + t32).astype(np.complex64)
+        for sv, cv, xv in ((sr, cr, t32.real), (si, ci, t32.imag)):
+            y = (xv - cv).astype(np.float32)
+            tt = (sv + y).astype(np.float32)
+            cv[:] = _bf16((tt - sv).astype(np.float32) - y)
+            sv[:] = tt
+    plain_err = rel(plain.astype(np.complex128), ref)
+    kahan_err = rel((sr + 1j * si).astype(np.complex128), ref)
+    print(f"compensated sum: device {dev_err:.2e}, host plain FP32 {plain_err:.2e}, "
+          f"host bf16-compensated {kahan_err:.2e}", flush=True)
+    bound = 5e-8
+    assert kahan_err <= bound
+    assert plain_err >= 4 * bound
+    assert dev_err <= bound
+
+
 @pytest.mark.parametrize("dt", ["c128", "c64"])
 @pytest.mark.parametrize("shape", [(9, 10, 12), (16, 16, 16), (5, 3, 33)])
 def test_ragged_3d(dev, shape, dt):

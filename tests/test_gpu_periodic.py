@@ -89,20 +89,21 @@ def test_periodic_spectrum_matches_oracle(dev, n):
 
 @pytest.mark.parametrize("dt", ["c128", "c64"])
 @pytest.mark.parametrize("case", ["homogeneous", "absorbing", "absorbing-dispersive", "inhomogeneous"])
-def test_fixed_iterations_match_oracle(dev, case, dt):
+def test_fixed_iterations_match_oracle(dev, case, dt, errlog):
     """Ten iterations (tol 0) on a 128^2 scaled setup: the iterate and the
     per-iteration stopping errors."""
     c = workloads.paper_periodic(case, 128)
     (p_ref, it_ref, e_ref), = oracle_run(c, 0.0, 10)
     p, it, e = gpu_run(dev, c, dt, 0.0, 10)
     assert it == it_ref == 10
-    assert rel(p[0], p_ref) <= TOL[dt] * (3 if dt == "c64" else 1)
+    tol = TOL[dt]
+    assert errlog("psi", rel(p[0], p_ref), tol) <= tol
     assert np.allclose(e, e_ref, rtol=1e-9 if dt == "c128" else 2e-3, atol=0)
 
 
 @pytest.mark.parametrize("dt", ["c128", "c64"])
 @pytest.mark.parametrize("case", ["homogeneous", "inhomogeneous"])
-def test_convergence_count_matches_oracle(dev, case, dt):
+def test_convergence_count_matches_oracle(dev, case, dt, errlog):
     """Run to the paper's tolerance 1e-5 on a 256^2 scaled setup: the same
     iteration count (FP32: within one, the stopping test being a
     floating-point comparison) and the same field."""
@@ -115,8 +116,10 @@ def test_convergence_count_matches_oracle(dev, case, dt):
         assert rel(p[0], p_ref) <= 1e-11
     else:
         assert abs(it - it_ref) <= 1
-        if it == it_ref:
-            assert rel(p[0], p_ref) <= 1e-5
+        if it != it_ref:
+            # the oracle's iterate after the GPU's count
+            (p_ref, _, _), = oracle_run(c, 0.0, it)
+        assert errlog("psi", rel(p[0], p_ref), 1e-5) <= 1e-5
 
 
 def test_batch_of_two_sources(dev):
@@ -148,7 +151,7 @@ def test_paper_homogeneous_4096(dev):
 
 
 @pytest.mark.parametrize("dt", ["c128", "c64"])
-def test_cbs_fixed_iterations_match_oracle(dev, dt):
+def test_cbs_fixed_iterations_match_oracle(dev, dt, errlog):
     """Convergent Born series on the paper's inhomogeneous setup (vs = 1800,
     eps = 0.8 k^2 >= max |k^2 - k0^2|), with the absorbing layer: ten updates."""
     import paper_2507_13754_amd as tbs
@@ -167,7 +170,8 @@ def test_cbs_fixed_iterations_match_oracle(dev, dt):
     psi, it, e = plan.iterate(torch.from_numpy(c.sources).to(dev, tdt(dt)), Vd, prof, prof, c.check_row,
                               0.0, 10, cbs=True)
     assert it == 10
-    assert rel(psi.cpu().numpy()[0], p_ref) <= TOL[dt] * (3 if dt == "c64" else 1)
+    tol = TOL[dt]
+    assert errlog("psi", rel(psi.cpu().numpy()[0], p_ref), tol) <= tol
     assert np.allclose(e, e_ref, rtol=1e-9 if dt == "c128" else 2e-3, atol=0)
     plan.close()
 
