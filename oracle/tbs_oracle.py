@@ -276,24 +276,33 @@ def solve(k0: complex, dx: float, s: np.ndarray, V: Optional[np.ndarray], nterms
 
 
 def density_operator(gamma: np.ndarray, dx: float, u: np.ndarray) -> np.ndarray:
-    """D(u) = div(gamma_rho grad u) on the physical 2D grid (the density term of
-    Sec. 2.1.3, Eq. acoustic_waveequn_time_dependent_inhomogeneous, with
-    gamma_rho = (rho_s - rho_f) / rho_s of Eq. mismatch_parameters), in
+    """D(u) = div(gamma_rho grad u) on the physical 2D or 3D grid (the density
+    term of Sec. 2.1.3, Eq. acoustic_waveequn_time_dependent_inhomogeneous,
+    with gamma_rho = (rho_s - rho_f) / rho_s of Eq. mismatch_parameters), in
     conservative second-order differences: per axis
     (g_{+1/2} (u_{+1} - u) - g_{-1/2} (u - u_{-1})) / dx^2 with g at the
     half points the mean of the two cells; u and gamma are 0 outside the grid.
-    ``u`` may carry leading batch axes."""
+    The grid has gamma.ndim axes (the trailing axes of ``u``, which may carry
+    leading batch axes); the axis terms are added x first, then y, then z."""
+    nd = gamma.ndim
     g = np.pad(np.asarray(gamma, dtype=np.float64), 1)
-    pad = [(0, 0)] * (u.ndim - 2) + [(1, 1), (1, 1)]
-    U = np.pad(u, pad)
-    c = U[..., 1:-1, 1:-1]
-    gc = g[1:-1, 1:-1]
-    gxp = 0.5 * (gc + g[1:-1, 2:])
-    gxm = 0.5 * (gc + g[1:-1, :-2])
-    gyp = 0.5 * (gc + g[2:, 1:-1])
-    gym = 0.5 * (gc + g[:-2, 1:-1])
-    return (gxp * (U[..., 1:-1, 2:] - c) - gxm * (c - U[..., 1:-1, :-2])
-            + gyp * (U[..., 2:, 1:-1] - c) - gym * (c - U[..., :-2, 1:-1])) / (dx * dx)
+    U = np.pad(u, [(0, 0)] * (u.ndim - nd) + [(1, 1)] * nd)
+    inner = tuple([slice(1, -1)] * nd)
+
+    def shifted(a, axis, k):
+        # a (padded) moved by k cells along grid axis ``axis``, cropped to the grid
+        sl = list(inner)
+        sl[axis] = slice(1 + k, a.shape[a.ndim - nd + axis] - 1 + k)
+        return a[(Ellipsis,) + tuple(sl)]
+
+    c = U[(Ellipsis,) + inner]
+    gc = g[inner]
+    out = 0.0
+    for axis in reversed(range(nd)):
+        gp = 0.5 * (gc + shifted(g, axis, 1))
+        gm = 0.5 * (gc + shifted(g, axis, -1))
+        out = out + gp * (shifted(U, axis, 1) - c) - gm * (c - shifted(U, axis, -1))
+    return out / (dx * dx)
 
 
 def born_series_density(apply_g: Callable[[np.ndarray], np.ndarray], s: np.ndarray, V: np.ndarray,
@@ -301,9 +310,11 @@ def born_series_density(apply_g: Callable[[np.ndarray], np.ndarray], s: np.ndarr
     """The series with a density contrast: the equation of Sec. 2.1.3 in the
     frequency domain, lap psi + k0^2 psi = -(s + V psi - div(gamma grad psi)),
     so u_0 = G s, u_n = G(V u_{n-1} - D(u_{n-1})), p = sum_{n<L} u_n, with the
-    same residuals as born_series (2D)."""
+    same residuals as born_series (2D or 3D: the grid axes of gamma)."""
+    axes = tuple(range(-gamma.ndim, 0))
+
     def norm(a):
-        return np.sqrt(np.sum(np.abs(a) ** 2, axis=(-2, -1)))
+        return np.sqrt(np.sum(np.abs(a) ** 2, axis=axes))
 
     u = apply_g(s)
     p = u.copy()
@@ -316,7 +327,7 @@ def born_series_density(apply_g: Callable[[np.ndarray], np.ndarray], s: np.ndarr
 
 
 def solve_density(k0: complex, dx: float, s: np.ndarray, V: np.ndarray, gamma: np.ndarray, nterms: int):
-    """FFT-evaluated series with a density contrast (2D)."""
+    """FFT-evaluated series with a density contrast (2D or 3D)."""
     G = GreenOperator(k0, dx, V.shape)
     return born_series_density(G, s, V, gamma, dx, nterms)
 

@@ -626,6 +626,72 @@ def test_density_operator_symmetric_negative():
     assert np.max(np.linalg.eigvalsh(Dm)) < 1e-12
 
 
+def test_density_operator_discrete_symbol_3d():
+    """3D: on a constant gamma, D acts on sin(a x) sin(b y) sin(c z) at interior
+    cells as gamma times -(4/dx^2)(sin^2(a dx/2) + sin^2(b dx/2) + sin^2(c dx/2))."""
+    n, dx, gam = 14, 0.4, 0.3
+    a, b, c = 0.8, 1.3, 2.1
+    z, y, x = np.mgrid[0:n, 0:n, 0:n] * dx
+    u = np.sin(a * x) * np.sin(b * y) * np.sin(c * z)
+    D = oracle.density_operator(np.full((n, n, n), gam), dx, u)
+    sym = -(4.0 / dx ** 2) * (np.sin(a * dx / 2) ** 2 + np.sin(b * dx / 2) ** 2 + np.sin(c * dx / 2) ** 2)
+    inner = (slice(1, -1),) * 3
+    assert np.allclose(D[inner], gam * sym * u[inner], rtol=0, atol=1e-12)
+    # each axis enters: a function of z alone sees only the z part of the symbol
+    uz = np.broadcast_to(np.sin(c * z[:, :1, :1]), (n, n, n)).copy()
+    Dz = oracle.density_operator(np.full((n, n, n), gam), dx, uz)
+    symz = -(4.0 / dx ** 2) * np.sin(c * dx / 2) ** 2
+    assert np.allclose(Dz[inner], gam * symz * uz[inner], rtol=0, atol=1e-12)
+
+
+def test_density_operator_second_order_3d():
+    """3D, smooth gamma and u: D(u) converges to the analytic div(gamma grad u)
+    at second order in dx."""
+    errs = []
+    for n in (16, 32, 64):
+        dx = 4.0 / n
+        z, y, x = np.mgrid[0:n, 0:n, 0:n] * dx + dx / 2
+        r2 = (x - 2) ** 2 + (y - 2) ** 2 + (z - 2) ** 2
+        gam = 0.3 * np.exp(-r2)
+        u = np.exp(1j * (1.1 * x + 0.4 * y - 0.7 * z)) * np.exp(-r2 / 2)
+        gx, gy, gz = gam * (-2 * (x - 2)), gam * (-2 * (y - 2)), gam * (-2 * (z - 2))
+        ux, uy, uz = u * (1.1j - (x - 2)), u * (0.4j - (y - 2)), u * (-0.7j - (z - 2))
+        uxx = ux * (1.1j - (x - 2)) - u
+        uyy = uy * (0.4j - (y - 2)) - u
+        uzz = uz * (-0.7j - (z - 2)) - u
+        exact = gx * ux + gy * uy + gz * uz + gam * (uxx + uyy + uzz)
+        D = oracle.density_operator(gam, dx, u)
+        inner = (slice(n // 8, -n // 8),) * 3
+        errs.append(np.max(np.abs(D[inner] - exact[inner])) / np.max(np.abs(exact[inner])))
+    assert errs[1] < 0.3 * errs[0] and errs[2] < 0.3 * errs[1], errs
+
+
+def test_density_operator_symmetric_negative_3d():
+    rng = np.random.default_rng(5)
+    gam = rng.uniform(0, 0.4, (4, 5, 6))
+    Dm = oracle.density_matrix(gam, 0.5)
+    assert np.allclose(Dm, Dm.T, atol=1e-14)
+    assert np.max(np.linalg.eigvalsh(Dm)) < 1e-12
+
+
+def test_density_series_converges_to_dense_solve_3d():
+    grid = (5, 6, 7)
+    dx = 1.0
+    k0 = 2 * np.pi / 6 * (1 + 0.03j)
+    V = 0.05 * (k0 * k0).real * workloads.random_field(grid, 23).real
+    zz, yy, xx = np.mgrid[0:grid[0], 0:grid[1], 0:grid[2]]
+    gam = 0.06 * np.exp(-((zz - 2) ** 2 + (yy - 3) ** 2 + (xx - 3) ** 2) / 4.0)
+    s = workloads.random_field(grid, 24)
+    A = oracle.dense_operator(k0, dx, grid)
+    Dm = oracle.density_matrix(gam, dx)
+    K = A @ (np.diag(V.ravel()) - Dm)
+    exact = np.linalg.solve(np.eye(K.shape[0]) - K, A @ s.ravel()).reshape(grid)
+    assert np.max(np.abs(np.linalg.eigvals(K))) < 0.6
+    p, res = oracle.solve_density(k0, dx, s, V, gam, 60)
+    assert rel(p, exact) < 1e-9
+    assert res[-1] < 1e-9
+
+
 def test_density_series_converges_to_dense_solve():
     """With a weak density and speed contrast the series converges to the
     dense solution of p = G (V - D) p + G s."""
