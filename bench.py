@@ -236,8 +236,6 @@ def run_broadband(dev, steps: int, warmup: int, fp64: bool, tune: bool):
             c = workloads.broadband(i)
             k0 = tbs.background_k0(c.omega, c.c0, c.alpha0, c.y)
             p = tbs.Plan(c.grid, c.dx, k0, dtype=dtype, batch=c.sources.shape[0]).tabulate()
-            if tune:
-                p.autotune()
             plans.append(p)
             srcs.append(torch.from_numpy(c.sources).to(dev, dtype))
             pots.append(p.potential(torch.from_numpy(c.c).to(dev), c.omega, c.c0, c.alpha0, c.y))
@@ -246,10 +244,14 @@ def run_broadband(dev, steps: int, warmup: int, fp64: bool, tune: bool):
                 geo.append((c.grid[1], c.grid[0], c.sources.shape[0], p.padded[0], p.padded[1]))
             L = c.nterms
             del c
-        t_build = time.perf_counter() - t0
-        log(f"[bench] broadband {name}: 48 plans built (tabulated{', tuned' if tune else ''}) in {t_build:.1f} s")
         batch = tbs.Batch(plans)
-        outs = batch.solve(srcs, pots, L)
+        outs = [torch.empty((p.batch,) + p.shape, dtype=dtype, device=dev) for p in plans]
+        if tune:
+            batch.autotune(srcs, pots, outs)
+        t_build = time.perf_counter() - t0
+        log(f"[bench] broadband {name}: 48 plans built (tabulated{', batch tuned' if tune else ''}) "
+            f"in {t_build:.1f} s")
+        outs = batch.solve(srcs, pots, L, outs=outs)
         ms, wall = time_fn(lambda: batch.solve(srcs, pots, L, outs=outs), steps, warmup)
         log(f"[bench] broadband {name}: {ms:.2f} ms/step ({wall:.2f} wall)")
         fp = name == "c128"

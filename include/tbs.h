@@ -142,9 +142,11 @@ int tbs_plan_set_stream(tbs_plan *plan, void *hip_stream);
  * (rows per row-pass block, columns per convolution block) on this plan's
  * shapes and keep the fastest.  The choice never changes the field arithmetic
  * (p_out is bitwise identical; the FP64 residual norms are summed in another
- * grouping and may differ in the last bits); it is cached per (device, grid, padded
- * lengths, batch, dtype) for the life of the process.  2D plans only (3D plans
- * keep the defaults).  Needs the spectrum (call after tbs_green_tabulate);
+ * grouping and may differ in the last bits); it is cached per (device model,
+ * grid, padded lengths, batch, dtype) for the life of the process and, when
+ * the environment variable TBS_TUNE_CACHE names a file, in that file (read on
+ * first use, one line appended per new choice).  2D plans only (3D plans keep
+ * the defaults).  Needs the spectrum (call after tbs_green_tabulate);
  * clobbers the plan's intermediate buffers; synchronous.  Outputs (may be
  * NULL): the chosen rows and columns per block. */
 int tbs_plan_autotune(tbs_plan *plan, int *row_nr_out, int *conv_nc_out);
@@ -237,18 +239,18 @@ int tbs_harmonic_source_scaled(tbs_plan *plan, int n, const void *const *fields,
                                const double *c_dev, double omega, double rho, double BA, void *S_out,
                                int *exp_out);
 
-/* Attach a density contrast to a 2D padded plan (NULL detaches): the term
+/* Attach a density contrast to a padded 2D or 3D plan (NULL detaches): the term
  * div(gamma grad psi) of the inhomogeneous wave equation (Sec. 2.1.3, Eqs.
  * acoustic_waveequn_time_dependent_inhomogeneous and mismatch_parameters,
  * gamma = (rho_s - rho_f) / rho_s; the paper drops it for rho_s ~ rho_f)
  * joins the potential of every term: u_n = G(V u_{n-1} - div(gamma grad
  * u_{n-1})), in conservative second-order differences with gamma at the half
  * points the mean of the two cells and zero outside the grid.
- *   gamma_dev: dev float64 [N_y][N_x], owned by the caller, read by every
+ *   gamma_dev: dev float64 [N_y][N_x] or [N_z][N_y][N_x], owned by the caller, read by every
  *              later tbs_solve until detached (the potential of tbs_solve
  *              may then be NULL: V = 0).
  * Each term then takes one more row pass (the field is kept in space between
- * them).  TBS_ERR_UNSUPPORTED on 3D or periodic plans; tbs_adjoint and
+ * them).  TBS_ERR_UNSUPPORTED on periodic plans; tbs_adjoint and
  * tbs_batch_create refuse plans with a density contrast. */
 int tbs_density_contrast(tbs_plan *plan, const double *gamma_dev);
 
@@ -361,6 +363,18 @@ int tbs_batch_create(tbs_batch **out, tbs_plan *const *plans, int nplans);
  * residual_out: host double [sum_i B_i][L] (plan order) or NULL. */
 int tbs_batch_solve(tbs_batch *batch, const void *const *sources, const void *const *potentials,
                     int nterms, void *const *p_outs, double *residual_out);
+
+/* Choose the block shapes of the batch's grouped launches (rows per row-pass
+ * block for all plans of one x length, columns per convolution block for all
+ * plans of one y length) by timing each bitwise-neutral candidate as one
+ * grouped launch on the given buffers (same meaning as in tbs_batch_solve;
+ * the contents of p_outs are undefined afterwards), and regroup.  Choices are
+ * kept per device model, dtype, length and member shapes for the life of the
+ * process, and in the file named by the environment variable TBS_TUNE_CACHE
+ * when it is set (read on first use, appended to; tbs_plan_autotune shares
+ * it).  Synchronises the first plan's stream; drops the recorded graph. */
+int tbs_batch_autotune(tbs_batch *batch, const void *const *sources, const void *const *potentials,
+                       void *const *p_outs);
 
 /* Release the batch (not its plans; NULL-safe). */
 void tbs_batch_destroy(tbs_batch *batch);

@@ -38,7 +38,7 @@ EXPORTS = (
     "tbs_batch_last_error", "tbs_plan_autotune", "tbs_green_periodic", "tbs_abl_profile",
     "tbs_kspace_coefficients", "tbs_density_contrast",
     "tbs_iterate", "tbs_batch_profile_enable", "tbs_batch_profile_read", "tbs_solve_noalloc",
-    "tbs_harmonic_source_scaled",
+    "tbs_harmonic_source_scaled", "tbs_batch_autotune",
 )
 PASS_KINDS = ("row_first", "row_mid", "row_last", "col_conv", "col_fwd", "col_inv")
 
@@ -108,6 +108,7 @@ def library() -> ctypes.CDLL:
         "tbs_batch_solve": (ctypes.c_int, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int,
                                            ctypes.POINTER(vp), dp]),
         "tbs_batch_destroy": (None, [vp]),
+        "tbs_batch_autotune": (ctypes.c_int, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp)]),
         "tbs_batch_profile_enable": (ctypes.c_int, [vp, ctypes.c_int]),
         "tbs_batch_profile_read": (ctypes.c_int, [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                                   ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
@@ -547,6 +548,20 @@ class Batch:
             warnings.warn(f"tbs_batch_solve: {L.tbs_status_string(rc).decode()}: "
                           f"{L.tbs_batch_last_error(self._h).decode()}", TBSWarning, stacklevel=2)
         return (outs, res) if residual else outs
+
+    def autotune(self, sources, potentials, outs):
+        """Pick the grouped launches' block shapes by timing them on these
+        buffers (bitwise-neutral; the contents of outs are undefined after)."""
+        n = len(self.plans)
+        sp = [_ptr(s, p.dtype, (p.batch,) + p.shape, "source") for p, s in zip(self.plans, sources)]
+        vp = [_ptr(v, p.dtype, p.shape, "potential") for p, v in zip(self.plans, potentials)]
+        op = [_ptr(o, p.dtype, (p.batch,) + p.shape, "out") for p, o in zip(self.plans, outs)]
+        A = ctypes.c_void_p * n
+        self.plans[0]._sync_stream()
+        L = library()
+        rc = L.tbs_batch_autotune(self._h, A(*sp), A(*vp), A(*op))
+        if rc != TBS_OK:
+            raise TBSError(rc, f"tbs_batch_autotune: {L.tbs_batch_last_error(self._h).decode()}")
 
     def profile(self, enable: bool = True):
         """Per-launch event timing of later solves (no graph replay meanwhile)."""

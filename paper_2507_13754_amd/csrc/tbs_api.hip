@@ -502,6 +502,92 @@ int forward_series(tbs_plan* p, const void* source, const void* V, int L, void* 
   return TBS_OK;
 }
 
+// ---------------------------------------------------------- tuning cache --
+// Block shapes chosen by the tuners, per device model and problem shape, kept
+// for the life of the process and, when the environment variable
+// TBS_TUNE_CACHE names a file, read from it on first use and appended to on
+// every new choice (one "key = values" line per choice; later lines win).
+struct TuneCache {
+  std::mutex mu;
+  bool loaded = false;
+  std::map<std::string, std::vector<int>> entries;
+};
+
+TuneCache& tune_cache() {
+  static TuneCache c;
+  return c;
+}
+
+std::string device_tag(int device) {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+    (void)hipGetLastError();
+    return "device" + std::to_string(device);
+  }
+  std::string arch = prop.gcnArchName;
+  for (char& ch : arch)
+    if (ch == ' ' || ch == '=') ch = '_';
+  return arch + "/" + std::to_string(prop.multiProcessorCount) + "cu";
+}
+
+void tune_cache_load(TuneCache& c) {  // caller holds c.mu
+  if (c.loaded) return;
+  c.loaded = true;
+  const char* path = std::getenv("TBS_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  char line[4096];
+  while (std::fgets(line, sizeof line, f)) {
+    const std::string sl(line);
+    const size_t eq = sl.find(" = ");
+    if (eq == std::string::npos) continue;
+    std::vector<int> vals;
+    const char* q = sl.c_str() + eq + 3;
+    while (true) {
+      char* end = nullptr;
+      const long v = std::strtol(q, &end, 10);
+      if (end == q) break;
+      vals.push_back((int)v);
+      q = end;
+    }
+    if (!vals.empty()) c.entries[sl.substr(0, eq)] = vals;
+  }
+  std::fclose(f);
+}
+
+bool tune_lookup(const std::string& key, std::vector<int>* vals) {
+  TuneCache& c = tune_cache();
+  std::lock_guard<std::mutex> g(c.mu);
+  tune_cache_load(c);
+  auto it = c.entries.find(key);
+  if (it == c.entries.end()) return false;
+  *vals = it->second;
+  return true;
+}
+
+void tune_store(const std::string& key, const std::vector<int>& vals) {
+  TuneCache& c = tune_cache();
+  std::lock_guard<std::mutex> g(c.mu);
+  tune_cache_load(c);
+  c.entries[key] = vals;
+  const char* path = std::getenv("TBS_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::string line = key + " =";
+  for (int v : vals) line += " " + std::to_string(v);
+  line += "\n";
+  std::fputs(line.c_str(), f);
+  std::fclose(f);
+}
+
+bool in_list(int v, const int* list, int n) {
+  for (int i = 0; i < n; ++i)
+    if (list[i] == v) return true;
+  return false;
+}
+
 int check_plan_ready(tbs_plan* p) {
   if (!p) return TBS_ERR_INVALID;
   if (p->periodic)
@@ -625,6 +711,74 @@ void batch_drop_graph(tbs_batch* b) {
   b->tables_ready = false;
   b->key.clear();
   b->key_L = 0;
+}
+
+// Group the batch's plans by padded length and block shape (rows: M_x and rows
+// per block; columns: M_y, layout block and columns per block) and upload the
+// block offsets of every group; called again after the shapes change.
+int batch_group(tbs_batch* b) {
+  const int nplans = (int)b->plans.size();
+  b->rgroups.clear();
+  b->cgroups.clear();
+  // group by padded length (rows: M_x; columns: M_y and the column shape)
+  b->rpos.assign(nplans, 0);
+  b->cpos.assign(nplans, 0);
+  auto find_or_add = [](std::vector<tbs_batch::Group>& gs, int chain, int M, int cb, int nc,
+                        int nr) -> tbs_batch::Group& {
+    for (auto& g : gs)
+      if (g.chain == chain && g.M == M && g.cb == cb && g.nc == nc && g.nr == nr) return g;
+    gs.push_back(tbs_batch::Group());
+    gs.back().chain = chain;
+    gs.back().M = M;
+    gs.back().cb = cb;
+    gs.back().nc = nc;
+    gs.back().nr = nr;
+    return gs.back();
+  };
+  for (int i = 0; i < nplans; ++i) {
+    tbs_plan* p = b->plans[i];
+    const int nr = p->row_nr ? p->row_nr : tbs::row_rows_per_block((int)p->M[0], p->fp64);
+    find_or_add(b->rgroups, b->chain_of[i], (int)p->M[0], p->cb, 0, nr).members.push_back(i);
+    int nc = 0;
+    (void)make_conv2d_args(p, false, &nc);
+    find_or_add(b->cgroups, b->chain_of[i], (int)p->M[1], p->cb, nc, 0).members.push_back(i);
+  }
+  std::vector<int> starts;
+  int pos = 0;
+  for (auto& g : b->rgroups) {
+    g.first = pos;
+    g.starts_off = (int)starts.size();
+    int acc = 0;
+    for (int i : g.members) {
+      b->rpos[i] = pos++;
+      starts.push_back(acc);
+      acc += row_blocks(b->plans[i]) * b->plans[i]->batch;
+    }
+    g.total = acc;
+  }
+  pos = 0;
+  for (auto& g : b->cgroups) {
+    g.first = pos;
+    g.starts_off = (int)starts.size();
+    int acc = 0;
+    for (int i : g.members) {
+      b->cpos[i] = pos++;
+      starts.push_back(acc);
+      int nc = 0;
+      const tbs::ColArgs c = make_conv2d_args(b->plans[i], false, &nc);
+      acc += c.nrhs * c.n1 * c.n0;
+    }
+    g.total = acc;
+  }
+  if (b->d_starts) (void)hipFree(b->d_starts);
+  b->d_starts = nullptr;
+  b->d_starts_bytes = starts.size() * sizeof(int);
+  if (hipMalloc(&b->d_starts, b->d_starts_bytes) != hipSuccess ||
+      hipMemcpy(b->d_starts, starts.data(), b->d_starts_bytes, hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipGetLastError();
+    return TBS_ERR_OOM;
+  }
+  return TBS_OK;
 }
 
 // Start event of a profiled launch (entry e); returns the end event to record
@@ -1082,8 +1236,7 @@ int tbs_green_tabulate(tbs_plan* p) {
 
 int tbs_density_contrast(tbs_plan* p, const double* gamma) {
   if (!p) return TBS_ERR_INVALID;
-  if (p->periodic || p->ndim != 2)
-    return fail(p, TBS_ERR_UNSUPPORTED, "the density term is built for 2D padded plans");
+  if (p->periodic) return fail(p, TBS_ERR_UNSUPPORTED, "the density term is built for padded plans");
   if (gamma && p->batch_refs > 0)
     return fail(p, TBS_ERR_STATE, "the plan belongs to a live batch (batches take no density term)");
   p->gamma = gamma;
@@ -1508,17 +1661,19 @@ int tbs_plan_autotune(tbs_plan* p, int* row_nr_out, int* conv_nc_out) {
   if (p->batch_refs > 0)
     return fail(p, TBS_ERR_STATE, "the plan belongs to a live batch (tune before tbs_batch_create)");
   if (p->ndim == 2) {
-    static std::mutex mu;
-    static std::map<std::vector<int64_t>, std::pair<int, int>> cache;
-    const std::vector<int64_t> key = {p->device, p->N[0], p->N[1], p->M[0], p->M[1], p->batch,
-                                      p->fp64 ? 1 : 0};
+    const std::string key = "plan " + device_tag(p->device) + " " + (p->fp64 ? "c128" : "c64") + " N" +
+                            std::to_string(p->N[0]) + "x" + std::to_string(p->N[1]) + " M" +
+                            std::to_string(p->M[0]) + "x" + std::to_string(p->M[1]) + " B" +
+                            std::to_string(p->batch);
     bool hit = false;
     {
-      std::lock_guard<std::mutex> g(mu);
-      auto it = cache.find(key);
-      if (it != cache.end()) {
-        p->row_nr = it->second.first;
-        p->conv_nc = it->second.second;
+      std::vector<int> v;
+      int cr[8], cc[8];
+      const int nrn = tbs::row_nr_candidates((int)p->M[0], p->fp64, cr);
+      const int ncn = tbs::conv_nc_candidates((int)p->M[1], p->fp64, p->cb, cc);
+      if (tune_lookup(key, &v) && v.size() == 2 && in_list(v[0], cr, nrn) && in_list(v[1], cc, ncn)) {
+        p->row_nr = v[0];
+        p->conv_nc = v[1];
         hit = true;
       }
     }
@@ -1595,8 +1750,7 @@ int tbs_plan_autotune(tbs_plan* p, int* row_nr_out, int* conv_nc_out) {
         p->conv_nc = 0;
         return rc;
       }
-      std::lock_guard<std::mutex> g(mu);
-      cache[key] = {p->row_nr, p->conv_nc};
+      tune_store(key, {p->row_nr, p->conv_nc});
     }
   }
   if (row_nr_out) *row_nr_out = p->row_nr ? p->row_nr : tbs::row_rows_per_block((int)p->M[0], p->fp64);
@@ -1686,61 +1840,10 @@ int tbs_batch_create(tbs_batch** out, tbs_plan* const* plans, int nplans) {
       w[c] += work(i);
     }
   }
-  // group by padded length (rows: M_x; columns: M_y and the column shape)
-  b->rpos.assign(nplans, 0);
-  b->cpos.assign(nplans, 0);
-  auto find_or_add = [](std::vector<tbs_batch::Group>& gs, int chain, int M, int cb, int nc,
-                        int nr) -> tbs_batch::Group& {
-    for (auto& g : gs)
-      if (g.chain == chain && g.M == M && g.cb == cb && g.nc == nc && g.nr == nr) return g;
-    gs.push_back(tbs_batch::Group());
-    gs.back().chain = chain;
-    gs.back().M = M;
-    gs.back().cb = cb;
-    gs.back().nc = nc;
-    gs.back().nr = nr;
-    return gs.back();
-  };
-  for (int i = 0; i < nplans; ++i) {
-    tbs_plan* p = b->plans[i];
-    find_or_add(b->rgroups, b->chain_of[i], (int)p->M[0], p->cb, 0, p->row_nr).members.push_back(i);
-    int nc = 0;
-    (void)make_conv2d_args(p, false, &nc);
-    find_or_add(b->cgroups, b->chain_of[i], (int)p->M[1], p->cb, nc, 0).members.push_back(i);
-  }
-  std::vector<int> starts;
-  int pos = 0;
-  for (auto& g : b->rgroups) {
-    g.first = pos;
-    g.starts_off = (int)starts.size();
-    int acc = 0;
-    for (int i : g.members) {
-      b->rpos[i] = pos++;
-      starts.push_back(acc);
-      acc += row_blocks(b->plans[i]) * b->plans[i]->batch;
-    }
-    g.total = acc;
-  }
-  pos = 0;
-  for (auto& g : b->cgroups) {
-    g.first = pos;
-    g.starts_off = (int)starts.size();
-    int acc = 0;
-    for (int i : g.members) {
-      b->cpos[i] = pos++;
-      starts.push_back(acc);
-      int nc = 0;
-      const tbs::ColArgs c = make_conv2d_args(b->plans[i], false, &nc);
-      acc += c.nrhs * c.n1 * c.n0;
-    }
-    g.total = acc;
-  }
-  b->d_starts_bytes = starts.size() * sizeof(int);
-  if (hipMalloc(&b->d_starts, b->d_starts_bytes) != hipSuccess ||
-      hipMemcpy(b->d_starts, starts.data(), b->d_starts_bytes, hipMemcpyHostToDevice) != hipSuccess) {
-    (void)hipGetLastError();
+  int grc = batch_group(b);
+  if (grc) {
     tbs_batch_destroy(b);
-    return fail(nullptr, TBS_ERR_OOM, "batch tables");
+    return fail(nullptr, grc, "batch tables");
   }
   for (tbs_plan* p : b->plans) p->batch_refs += 1;
   b->counted = true;
@@ -1883,6 +1986,176 @@ int tbs_batch_solve(tbs_batch* b, const void* const* sources, const void* const*
     off += (size_t)p->batch * L;
   }
   return warn;
+}
+
+int tbs_batch_autotune(tbs_batch* b, const void* const* sources, const void* const* potentials,
+                       void* const* p_outs) {
+  if (!b) return TBS_ERR_INVALID;
+  if (!sources || !potentials || !p_outs) return bfail(b, TBS_ERR_INVALID, "NULL pointer array");
+  const int np = (int)b->plans.size();
+  for (int i = 0; i < np; ++i)
+    if (!sources[i] || !potentials[i] || !p_outs[i])
+      return bfail(b, TBS_ERR_INVALID, "batch tuning needs source, potential and output per plan");
+  if (hipStreamSynchronize(b->stream) != hipSuccess ||
+      (b->stream2 && hipStreamSynchronize(b->stream2) != hipSuccess))
+    return bfail(b, TBS_ERR_HIP, "batch: previous solve failed");
+  batch_drop_graph(b);
+  const hipStream_t s = b->plans[0]->stream;
+  for (tbs_plan* p : b->plans) {
+    // norm partials of one row pass for any block shape (at most one row per block)
+    if (ensure_doubles(p, &p->partials, &p->partials_cap, (size_t)2 * p->batch * p->N[1]))
+      return bfail(b, TBS_ERR_OOM, p->err);
+  }
+  const std::string tag = device_tag(b->plans[0]->device) + (b->fp64 ? " c128" : " c64");
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  void* d_desc = nullptr;
+  void* d_st = nullptr;
+  const size_t desc_bytes = (size_t)np * std::max(sizeof(tbs::RowArgs), sizeof(tbs::ColArgs));
+  int rc = TBS_OK;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess ||
+      hipMalloc(&d_desc, desc_bytes) != hipSuccess || hipMalloc(&d_st, (size_t)np * sizeof(int)) != hipSuccess) {
+    (void)hipGetLastError();
+    rc = bfail(b, TBS_ERR_OOM, "batch tuning buffers");
+  }
+  // time one grouped launch over all plans of one length (2 warm-up, 3 timed)
+  auto timeit = [&](auto&& launch) -> double {
+    for (int w = 0; w < 2; ++w) launch();
+    (void)hipEventRecord(e0, s);
+    for (int r = 0; r < 3; ++r) launch();
+    (void)hipEventRecord(e1, s);
+    if (hipEventSynchronize(e1) != hipSuccess) return 1e30;
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    return ms / 3.0;
+  };
+  // rows: one choice of rows per block for all plans of one x length
+  std::map<int, std::vector<int>> by_row;
+  std::map<std::pair<int, int>, std::vector<int>> by_col;
+  for (int i = 0; i < np; ++i) {
+    by_row[(int)b->plans[i]->M[0]].push_back(i);
+    by_col[{(int)b->plans[i]->M[1], b->plans[i]->cb}].push_back(i);
+  }
+  auto members_key = [&](const std::vector<int>& mem) {
+    std::vector<std::string> parts;
+    for (int i : mem)
+      parts.push_back(std::to_string(b->plans[i]->N[0]) + "x" + std::to_string(b->plans[i]->N[1]) + "x" +
+                      std::to_string(b->plans[i]->batch));
+    std::sort(parts.begin(), parts.end());
+    std::string k;
+    for (const auto& q : parts) k += (k.empty() ? "" : ",") + q;
+    return k;
+  };
+  for (auto it = by_row.begin(); !rc && it != by_row.end(); ++it) {
+    const int M = it->first;
+    const std::vector<int>& mem = it->second;
+    int cand[8];
+    const int n = tbs::row_nr_candidates(M, b->fp64, cand);
+    const std::string key = "batchrow " + tag + " M" + std::to_string(M) + " " + members_key(mem);
+    std::vector<int> v;
+    int pick = cand[0];
+    if (tune_lookup(key, &v) && v.size() == 1 && in_list(v[0], cand, n)) {
+      pick = v[0];
+    } else if (n > 1) {
+      double best = 1e30;
+      for (int ci = 0; ci < n && !rc; ++ci) {
+        std::vector<tbs::RowArgs> d;
+        std::vector<int> st;
+        int total = 0;
+        for (int i : mem) {
+          tbs_plan* p = b->plans[i];
+          p->row_nr = cand[ci];
+          d.push_back(make_row_args(p, tbs::ROW_IN_SPECTRAL, tbs::ACC_ADD, 1, false, nullptr, potentials[i],
+                                    p_outs[i], nullptr, nullptr, nullptr, p->partials));
+          st.push_back(total);
+          total += row_blocks(p) * p->batch;
+        }
+        if (hipMemcpy(d_desc, d.data(), d.size() * sizeof(tbs::RowArgs), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(d_st, st.data(), st.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
+          (void)hipGetLastError();
+          rc = bfail(b, TBS_ERR_HIP, "batch tuning tables");
+          break;
+        }
+        int le = 0;
+        const double t = timeit([&] {
+          const int e = tbs::launch_row_group(b->fp64, M, b->plans[mem[0]]->cb, cand[ci],
+                                              (const tbs::RowArgs*)d_desc, (const int*)d_st, (int)mem.size(),
+                                              total, s);
+          if (e) le = e;
+        });
+        if (le) {
+          rc = bfail(b, TBS_ERR_HIP, std::string("batch tuning launch: ") + hipGetErrorString((hipError_t)le));
+          break;
+        }
+        if (t < best) {
+          best = t;
+          pick = cand[ci];
+        }
+      }
+      if (!rc) tune_store(key, {pick});
+    }
+    for (int i : mem) b->plans[i]->row_nr = pick;
+  }
+  // columns: one choice of columns per block for all plans of one y length
+  for (auto it = by_col.begin(); !rc && it != by_col.end(); ++it) {
+    const int M = it->first.first;
+    const int cb = it->first.second;
+    const std::vector<int>& mem = it->second;
+    int cand[8];
+    const int n = tbs::conv_nc_candidates(M, b->fp64, cb, cand);
+    const std::string key = "batchcol " + tag + " M" + std::to_string(M) + " cb" + std::to_string(cb) + " " +
+                            members_key(mem);
+    std::vector<int> v;
+    int pick = cand[0];
+    if (tune_lookup(key, &v) && v.size() == 1 && in_list(v[0], cand, n)) {
+      pick = v[0];
+    } else if (n > 1) {
+      double best = 1e30;
+      for (int ci = 0; ci < n && !rc; ++ci) {
+        std::vector<tbs::ColArgs> d;
+        std::vector<int> st;
+        int total = 0;
+        for (int i : mem) {
+          tbs_plan* p = b->plans[i];
+          p->conv_nc = cand[ci];
+          int nc = 0;
+          d.push_back(make_conv2d_args(p, false, &nc));
+          st.push_back(total);
+          total += d.back().nrhs * d.back().n1 * d.back().n0;
+        }
+        if (hipMemcpy(d_desc, d.data(), d.size() * sizeof(tbs::ColArgs), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(d_st, st.data(), st.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
+          (void)hipGetLastError();
+          rc = bfail(b, TBS_ERR_HIP, "batch tuning tables");
+          break;
+        }
+        int le = 0;
+        const double t = timeit([&] {
+          const int e = tbs::launch_col_group(b->fp64, M, cand[ci], (const tbs::ColArgs*)d_desc,
+                                              (const int*)d_st, (int)mem.size(), total, s);
+          if (e) le = e;
+        });
+        if (le) {
+          rc = bfail(b, TBS_ERR_HIP, std::string("batch tuning launch: ") + hipGetErrorString((hipError_t)le));
+          break;
+        }
+        if (t < best) {
+          best = t;
+          pick = cand[ci];
+        }
+      }
+      if (!rc) tune_store(key, {pick});
+    }
+    for (int i : mem) b->plans[i]->conv_nc = pick;
+  }
+  if (hipStreamSynchronize(s) != hipSuccess && !rc) rc = bfail(b, TBS_ERR_HIP, "batch tuning");
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (d_desc) (void)hipFree(d_desc);
+  if (d_st) (void)hipFree(d_st);
+  // regroup with the chosen shapes (also after a failure: shapes may have moved)
+  const int grc = batch_group(b);
+  if (!rc && grc) rc = bfail(b, grc, "batch tables");
+  return rc;
 }
 
 int tbs_batch_profile_enable(tbs_batch* b, int enable) {

@@ -58,7 +58,7 @@
 #define TBS_OCC_HINT 1      // size each pass's register budget to its LDS occupancy
 #endif
 #ifndef TBS_PREFETCH
-#define TBS_PREFETCH 0      // loads issued with the line's own: 1 row sum + compensation,
+#define TBS_PREFETCH 1      // loads issued with the line's own: 1 row sum + compensation,
 #endif                      // 2 row potential, 4 column spectrum
 #define TBS_PF_ACC ((TBS_PREFETCH & 1) != 0)
 #define TBS_PF_V ((TBS_PREFETCH & 2) != 0)
@@ -105,31 +105,43 @@ __device__ __forceinline__ int mirror_pair(int l, int n) {
   return (l & 1) ? k : n - k;
 }
 
-// Density term div(gamma grad u) at cell (y, x) of a 2D field u (the term of
-// the inhomogeneous wave equation of Sec. 2.1.3 that carries the density
-// contrast gamma = (rho_s - rho_f) / rho_s): conservative second-order
-// differences with gamma at the half points the mean of the two cells, u and
-// gamma zero outside the grid.  c = u(y, x).  FP64 arithmetic.
+// Density term div(gamma grad u) at cell (z, y, x) of a 2D (nz = 1) or 3D
+// field u (the term of the inhomogeneous wave equation of Sec. 2.1.3 that
+// carries the density contrast gamma = (rho_s - rho_f) / rho_s): conservative
+// second-order differences per axis with gamma at the half points the mean of
+// the two cells, u and gamma zero outside the grid; the axis terms are added
+// x, y, z in that order.  i: index of the cell in u, c = u(z, y, x).  FP64
+// arithmetic.
 template <typename T>
 __device__ __forceinline__ cx<T> density_term(const RowArgs& a, const void* u,
-                                              int64_t i, int y, int x, cx<T> c) {
+                                              int64_t i, int z, int y, int x, cx<T> c) {
   const double* g = a.gamma;
-  const int64_t gi = (int64_t)y * a.nx + x;
+  const int64_t sy = a.nx, sz = (int64_t)a.nx * a.ny;
+  const int64_t gi = ((int64_t)z * a.ny + y) * a.nx + x;
   const double gc = gld1<double>(g, gi);
   const bool xp = x + 1 < a.nx, xm = x > 0, yp = y + 1 < a.ny, ym = y > 0;
+  const bool zp = z + 1 < a.nz, zm = z > 0;
   const double gxp = 0.5 * (gc + (xp ? gld1<double>(g, gi + 1) : 0.0));
   const double gxm = 0.5 * (gc + (xm ? gld1<double>(g, gi - 1) : 0.0));
-  const double gyp = 0.5 * (gc + (yp ? gld1<double>(g, gi + a.nx) : 0.0));
-  const double gym = 0.5 * (gc + (ym ? gld1<double>(g, gi - a.nx) : 0.0));
-  if (gxp == 0.0 && gxm == 0.0 && gyp == 0.0 && gym == 0.0) return cx<T>{T(0), T(0)};
-  const cx<T> z = {T(0), T(0)};
-  const cx<T> uxp = xp ? gld<T>(u, i + 1) : z, uxm = xm ? gld<T>(u, i - 1) : z;
-  const cx<T> uyp = yp ? gld<T>(u, i + a.nx) : z, uym = ym ? gld<T>(u, i - a.nx) : z;
+  const double gyp = 0.5 * (gc + (yp ? gld1<double>(g, gi + sy) : 0.0));
+  const double gym = 0.5 * (gc + (ym ? gld1<double>(g, gi - sy) : 0.0));
+  const double gzp = a.nz > 1 ? 0.5 * (gc + (zp ? gld1<double>(g, gi + sz) : 0.0)) : 0.0;
+  const double gzm = a.nz > 1 ? 0.5 * (gc + (zm ? gld1<double>(g, gi - sz) : 0.0)) : 0.0;
+  if (gxp == 0.0 && gxm == 0.0 && gyp == 0.0 && gym == 0.0 && gzp == 0.0 && gzm == 0.0)
+    return cx<T>{T(0), T(0)};
+  const cx<T> zero = {T(0), T(0)};
+  const cx<T> uxp = xp ? gld<T>(u, i + 1) : zero, uxm = xm ? gld<T>(u, i - 1) : zero;
+  const cx<T> uyp = yp ? gld<T>(u, i + sy) : zero, uym = ym ? gld<T>(u, i - sy) : zero;
   const double cr = c.x, ci = c.y;
-  const double re = gxp * ((double)uxp.x - cr) - gxm * (cr - (double)uxm.x) +
-                    gyp * ((double)uyp.x - cr) - gym * (cr - (double)uym.x);
-  const double im = gxp * ((double)uxp.y - ci) - gxm * (ci - (double)uxm.y) +
-                    gyp * ((double)uyp.y - ci) - gym * (ci - (double)uym.y);
+  double re = gxp * ((double)uxp.x - cr) - gxm * (cr - (double)uxm.x);
+  double im = gxp * ((double)uxp.y - ci) - gxm * (ci - (double)uxm.y);
+  re += gyp * ((double)uyp.x - cr) - gym * (cr - (double)uym.x);
+  im += gyp * ((double)uyp.y - ci) - gym * (ci - (double)uym.y);
+  if (a.nz > 1) {
+    const cx<T> uzp = zp ? gld<T>(u, i + sz) : zero, uzm = zm ? gld<T>(u, i - sz) : zero;
+    re += gzp * ((double)uzp.x - cr) - gzm * (cr - (double)uzm.x);
+    im += gzp * ((double)uzp.y - ci) - gzm * (ci - (double)uzm.y);
+  }
   return cx<T>{(T)(re * a.inv_dx2), (T)(im * a.inv_dx2)};
 }
 
@@ -343,7 +355,7 @@ __device__ __forceinline__ void row_pass_body(const RowArgs& a, const int lb) {
           } else {
             w = cx<T>{T(0), T(0)};
           }
-          if (a.gamma != nullptr) w = w - density_term(a, src, sp_base + x, yy, x, u0);
+          if (a.gamma != nullptr) w = w - density_term<T>(a, src, sp_base + x, zz, yy, x, u0);
         }
       }
       v[j] = w;

@@ -154,3 +154,27 @@ def test_two_launch_chains_are_bitwise_one(dev, monkeypatch):
     two.close()
     for p in plans:
         p.close()
+
+
+def test_batch_autotune_is_bitwise_neutral_and_cached(dev, tmp_path, monkeypatch):
+    """tbs_batch_autotune times the grouped launches' block shapes and
+    regroups: the fields after tuning equal the untuned ones bitwise, and the
+    choices land in the TBS_TUNE_CACHE file."""
+    import paper_2507_13754_amd as tbs
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("TBS_TUNE_CACHE", str(cache))
+    cs = cases(nangles=2, nterms=5)
+    plans, srcs, pots = build(dev, cs, "c64")
+    batch = tbs.Batch(plans)
+    ref = [o.clone() for o in batch.solve(srcs, pots, 5)]
+    outs = [torch.empty_like(o) for o in ref]
+    batch.autotune(srcs, pots, outs)
+    got = batch.solve(srcs, pots, 5, outs=outs)
+    for a, b in zip(ref, got):
+        assert torch.equal(a, b)
+    batch.close()
+    lines = cache.read_text().splitlines() if cache.exists() else []
+    # only lengths with more than one candidate shape are timed and stored
+    assert all(" = " in ln and ln.split()[0] in ("batchrow", "batchcol") for ln in lines)
+    for p in plans:
+        p.close()

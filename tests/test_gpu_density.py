@@ -27,16 +27,19 @@ def rel(a, b):
     return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
 
 
-def blob(shape, amp, cy, cx, r2):
-    yy, xx = np.mgrid[0:shape[0], 0:shape[1]]
-    return amp * np.exp(-((yy - cy) ** 2 + (xx - cx) ** 2) / r2)
+def blob(shape, amp, centre, r2):
+    """amp exp(-|i - centre|^2 / r2) on a 2D or 3D grid of cells."""
+    idx = np.indices(shape)
+    d2 = sum((idx[a] - centre[a]) ** 2 for a in range(len(shape)))
+    return amp * np.exp(-d2 / r2)
 
 
 def case(shape, seed):
     dx = 1.0
     k0 = 2 * np.pi / 6.0 * (1 + 0.01j)
     V = 0.04 * (k0 * k0).real * workloads.random_field(shape, seed)
-    gam = blob(shape, 0.08, shape[0] / 2, shape[1] / 3, shape[0])
+    centre = [n / 2 for n in shape[:-1]] + [shape[-1] / 3]
+    gam = blob(shape, 0.08, centre, shape[0])
     s = workloads.random_field((2,) + tuple(shape), seed + 1)
     return dx, k0, V, gam, s
 
@@ -54,7 +57,7 @@ def gpu(dev, shape, dx, k0, s, V, gam, L, dt):
 
 
 @pytest.mark.parametrize("dt", ["c128", "c64"])
-@pytest.mark.parametrize("shape", [(37, 23), (64, 96), (130, 70)])
+@pytest.mark.parametrize("shape", [(37, 23), (64, 96), (130, 70), (9, 10, 12), (12, 7, 16), (5, 3, 20)])
 def test_density_series_matches_oracle(dev, shape, dt):
     dx, k0, V, gam, s = case(shape, sum(shape))
     L = 7
@@ -89,7 +92,7 @@ def test_density_512_fp32(dev):
     c = workloads.plain2d(n=512, nterms=20)
     k0 = oracle.background_k0(c.omega, c.c0, c.alpha0, c.y)
     V = oracle.potential(c.c, c.omega, c.c0, c.alpha0, c.y)
-    gam = blob((512, 512), 0.1, 300, 256, 400.0)
+    gam = blob((512, 512), 0.1, (300, 256), 400.0)
     p_ref, _ = oracle.solve_density(k0, c.dx, c.sources, V, gam, c.nterms)
     plan = tbs.Plan(c.grid, c.dx, tbs.background_k0(c.omega, c.c0, c.alpha0, c.y),
                     dtype=torch.complex64).tabulate()
@@ -100,11 +103,35 @@ def test_density_512_fp32(dev):
     plan.close()
 
 
+def test_density_3d_fp32_medium(dev):
+    """A 64^3 grid at 6 points per wavelength with a 5 % density blob and a
+    2 % speed medium, 12 terms, FP32 against the oracle."""
+    import paper_2507_13754_amd as tbs
+    n = 64
+    f = 3e6
+    dx = workloads.C0 / f / 6
+    om = 2 * np.pi * f
+    a0, y = workloads.alpha0_si(0.75, 1.5), 1.5
+    c = workloads.small_medium((n, n, n), dx, 0.02, seed=71)
+    gam = blob((n, n, n), 0.05, (n / 2, n / 2, n / 3), 60.0)
+    s = np.zeros((1, n, n, n), np.complex128)
+    s[0, 8, n // 2, 20:44:3] = 1.0 / dx ** 3
+    k0 = oracle.background_k0(om, workloads.C0, a0, y)
+    V = oracle.potential(c, om, workloads.C0, a0, y)
+    p_ref, _ = oracle.solve_density(k0, dx, s, V, gam, 12)
+    plan = tbs.Plan((n, n, n), dx, tbs.background_k0(om, workloads.C0, a0, y), dtype=torch.complex64).tabulate()
+    plan.density_contrast(torch.from_numpy(gam).to(dev))
+    Vg = plan.potential(torch.from_numpy(c).to(dev), om, workloads.C0, a0, y)
+    p = plan.solve(torch.from_numpy(s).to(dev, torch.complex64), Vg, 12)
+    assert rel(p.cpu().numpy().astype(np.complex128)[0], p_ref[0]) <= 1e-5
+    plan.close()
+
+
 def test_density_refusals(dev):
     import paper_2507_13754_amd as tbs
-    plan = tbs.Plan((8, 10, 12), 1.0, 1.0 + 0.1j, dtype=torch.complex64)
+    plan = tbs.Plan((16, 16), 1.0, 1.0 + 0.1j, padding=1, dtype=torch.complex64)
     with pytest.raises(tbs.TBSError) as e:
-        plan.density_contrast(torch.zeros((8, 10, 12), dtype=torch.float64, device=dev))
+        plan.density_contrast(torch.zeros((16, 16), dtype=torch.float64, device=dev))
     assert e.value.status == -2
     plan.close()
     shape = (20, 24)
