@@ -423,7 +423,7 @@ def run_absorb2d(dev, steps: int, warmup: int, fp64: bool, tune: bool):
     return out
 
 
-def run_harmonic3d(dev, steps: int, warmup: int, fp64: bool):
+def run_harmonic3d(dev, steps: int, warmup: int, fp64: bool, tune: bool):
     """256^3 at lambda/6 (3 MHz), 3D blob tissue; fundamental (24 terms), the
     second-harmonic source, then the 6 MHz solve (24 terms).  One step = both
     series and the source kernel."""
@@ -442,6 +442,7 @@ def run_harmonic3d(dev, steps: int, warmup: int, fp64: bool):
             continue
         p1 = tbs.Plan(c.grid, c.dx, tbs.background_k0(om, c.c0, c.alpha0, c.y), dtype=dtype).tabulate()
         p2 = tbs.Plan(c.grid, c.dx, tbs.background_k0(2 * om, c.c0, c.alpha0, c.y), dtype=dtype).tabulate()
+        shapes = [p1.autotune()[1], p2.autotune()[1]] if tune else None  # z lines per block
         V1 = p1.potential(cd, om, c.c0, c.alpha0, c.y)
         V2 = p2.potential(cd, 2 * om, c.c0, c.alpha0, c.y)
         s = torch.from_numpy(c.sources).to(dev, dtype)
@@ -465,7 +466,8 @@ def run_harmonic3d(dev, steps: int, warmup: int, fp64: bool):
         log(f"[bench] harmonic3d {name}: {ms:.2f} ms/step")
         outs[name] = (f1.cpu().numpy(), f2.cpu().numpy())
         entry = {"value": gpt / (ms * 1e-3), "ms_per_step": ms, "alg_bytes_per_step": nb,
-                 "achieved_GBps": nb / (ms * 1e-3) / 1e9, "frac": nb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+                 "achieved_GBps": nb / (ms * 1e-3) / 1e9, "frac": nb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                 "autotuned_z_lines_per_block": shapes}
         if name == "c64":
             res.update(entry)
         else:
@@ -892,7 +894,7 @@ def main():
     if "absorb2d" in extras:
         sw["absorb2d"] = run_absorb2d(dev, max(10, args.steps), args.warmup, fp64, tune)
     if "harmonic3d" in extras:
-        sw["harmonic3d"] = run_harmonic3d(dev, max(2, args.steps // 4), 1, fp64)
+        sw["harmonic3d"] = run_harmonic3d(dev, max(2, args.steps // 4), 1, fp64, tune)
     if "adjoint2d" in extras:
         sw["adjoint2d"] = run_adjoint2d(dev, 2, 1, fp64)
     if "density2d" in extras:

@@ -139,14 +139,13 @@ int tbs_plan_info(const tbs_plan *plan, int64_t padded_out[3], int64_t *device_b
 int tbs_plan_set_stream(tbs_plan *plan, void *hip_stream);
 
 /* Autotuner: time the block-shape candidates of the row and column passes
- * (rows per row-pass block, columns per convolution block) on this plan's
- * shapes and keep the fastest.  The choice never changes the field arithmetic
+ * (2D: rows per row-pass block and columns per convolution block; 3D: z lines
+ * per block of the z convolution) on this plan's shapes and keep the fastest.  The choice never changes the field arithmetic
  * (p_out is bitwise identical; the FP64 residual norms are summed in another
  * grouping and may differ in the last bits); it is cached per (device model,
  * grid, padded lengths, batch, dtype) for the life of the process and, when
  * the environment variable TBS_TUNE_CACHE names a file, in that file (read on
- * first use, one line appended per new choice).  2D plans only (3D plans keep
- * the defaults).  Needs the spectrum (call after tbs_green_tabulate);
+ * first use, one line appended per new choice).  Needs the spectrum (call after tbs_green_tabulate);
  * clobbers the plan's intermediate buffers; synchronous.  Outputs (may be
  * NULL): the chosen rows and columns per block. */
 int tbs_plan_autotune(tbs_plan *plan, int *row_nr_out, int *conv_nc_out);

@@ -63,8 +63,9 @@ void dft_rt(int R, tbs::cx<double>* a) {
 // Runs the device transform's data flow on the host: TPT = M/E emulated
 // threads with E registers each in the strided layout, every stage's
 // butterflies, and between stages either the exchange through a shared
-// array (stage_out_index, read back strided) or, for local stages, the
-// register renaming local_register.  out receives the transform (natural
+// array at the slots the device uses for 8-byte elements (xwrite_slot,
+// read back at xread_slot) or, for local stages, the register renaming
+// local_register.  out receives the transform (natural
 // order); *n_exchanges / *n_local count the two kinds of hand-over.
 extern "C" int tbs_hostcheck_fft(int M, int E, int inv, const double* in, double* out,
                                  int* n_exchanges, int* n_local) {
@@ -72,7 +73,7 @@ extern "C" int tbs_hostcheck_fft(int M, int E, int inv, const double* in, double
   const tbs::Stages st = tbs::make_stages(M, E);
   if (st.n <= 0) return -1;
   const int TPT = M / E;
-  std::vector<tbs::cx<double>> v((size_t)M), w((size_t)M), sh((size_t)M);
+  std::vector<tbs::cx<double>> v((size_t)M), w((size_t)M), sh((size_t)tbs::lds_len(M, 1, 8));
   for (int t = 0; t < TPT; ++t)
     for (int j = 0; j < E; ++j) v[(size_t)t * E + j] = {in[2 * (t + j * TPT)], in[2 * (t + j * TPT) + 1]};
   int L = 1;
@@ -84,6 +85,7 @@ extern "C" int tbs_hostcheck_fft(int M, int E, int inv, const double* in, double
     const int NB = E / R;
     const bool last = S + 1 == st.n;
     const bool local = tbs::stage_is_local(M, E, S);
+    const tbs::Swz xl = tbs::swz_of(M, TPT, L, R, 16);
     for (int t = 0; t < TPT; ++t) {
       for (int q = 0; q < NB; ++q) {
         const int b = t + q * TPT;
@@ -100,13 +102,13 @@ extern "C" int tbs_hostcheck_fft(int M, int E, int inv, const double* in, double
         for (int r = 0; r < R; ++r) {
           if (last) w[(size_t)t * E + q + r * NB] = a[r];
           else if (local) w[(size_t)t * E + tbs::local_register(q, r, TPT, L, R)] = a[r];
-          else sh[(size_t)tbs::stage_out_index(b, L, R, r)] = a[r];
+          else sh[(size_t)tbs::xwrite_slot(xl, TPT, L, R, t, q, r)] = a[r];
         }
       }
     }
     if (!last && !local) {
       for (int t = 0; t < TPT; ++t)
-        for (int j = 0; j < E; ++j) w[(size_t)t * E + j] = sh[(size_t)(t + j * TPT)];
+        for (int j = 0; j < E; ++j) w[(size_t)t * E + j] = sh[(size_t)tbs::xread_slot(xl, TPT, t, j)];
       ++*n_exchanges;
     } else if (local) {
       ++*n_local;
@@ -142,6 +144,94 @@ extern "C" int tbs_hostcheck_slots(int M, int E) {
           for (int r = 0; r < R; ++r)
             bad += tbs::write_slot(TPT, L, R, t, q, r) !=
                    tbs::lpad(tbs::stage_out_index(t + q * TPT, L, R, r));
+    L *= R;
+  }
+  return bad;
+}
+
+// The XOR exchange layouts (swz_of / xwrite_slot / xread_slot) for LDS
+// elements of esz bytes: the closed forms equal the layout applied to the
+// defining index, the write slots of a stage are distinct and inside the
+// line's slots, and every read finds the element it stands for.  Bank model
+// of gfx950's LDS: 32 banks of 4 bytes, 128 / esz lanes of one instruction
+// served per cycle, an access of esz bytes covering esz / 4 consecutive
+// banks; lanes of one group on the same bank at different addresses cost
+// one extra cycle each.  *cyc_pad / *cyc_xor: the extra cycles of all the
+// exchanges of one line (waves of 64 lanes) with the padded layout and with
+// the layout the device uses.  Returns the number of mismatches.
+namespace {
+int extra_cycles(const std::vector<int>& slot, int esz) {
+  const int G = 128 / esz, words = esz / 4;
+  int extra = 0;
+  for (size_t g0 = 0; g0 < slot.size(); g0 += (size_t)G) {
+    std::vector<std::vector<int>> bank(32);
+    for (size_t i = g0; i < g0 + (size_t)G && i < slot.size(); ++i)
+      for (int d = 0; d < words; ++d) {
+        const int a = slot[i] * words + d;
+        auto& b = bank[(size_t)(a % 32)];
+        bool seen = false;
+        for (int x : b) seen |= (x == a);
+        if (!seen) b.push_back(a);
+      }
+    int worst = 1;
+    for (auto& b : bank) worst = (int)b.size() > worst ? (int)b.size() : worst;
+    extra += worst - 1;
+  }
+  return extra;
+}
+}  // namespace
+
+extern "C" int tbs_hostcheck_xslots(int M, int E, int esz, int* cyc_pad, int* cyc_xor) {
+  const tbs::Stages st = tbs::make_stages(M, E);
+  if (st.n <= 0 || M % E || (esz != 4 && esz != 8 && esz != 16)) return -1;
+  const int TPT = M / E;
+  const int len = tbs::lds_len(M, 1, esz);
+  int bad = 0;
+  *cyc_pad = 0;
+  *cyc_xor = 0;
+  int L = 1;
+  for (int S = 0; S + 1 < st.n; ++S) {
+    const int R = st.r[S];
+    if (!tbs::stage_is_local(M, E, S)) {
+      const tbs::Swz xl = tbs::swz_of(M, TPT, L, R, 128 / esz);
+      const tbs::Swz pad{0, -1, 0};
+      std::vector<int> at((size_t)M, -1);   // element -> slot
+      std::vector<int> owner((size_t)len, -1);
+      for (int q = 0; q < E / R; ++q)
+        for (int r = 0; r < R; ++r) {
+          std::vector<int> wp, wx;
+          for (int t = 0; t < TPT; ++t) {
+            const int e = tbs::stage_out_index(t + q * TPT, L, R, r);
+            const int sx = tbs::xwrite_slot(xl, TPT, L, R, t, q, r);
+            const int want = xl.nb < 0 ? tbs::lpad(e) : tbs::swz_apply(e, xl);
+            bad += sx != want;
+            if (sx < 0 || sx >= len || owner[(size_t)sx] >= 0) { ++bad; continue; }
+            owner[(size_t)sx] = e;
+            at[(size_t)e] = sx;
+            wp.push_back(tbs::xwrite_slot(pad, TPT, L, R, t, q, r));
+            wx.push_back(sx);
+          }
+          for (size_t w0 = 0; w0 < wx.size(); w0 += 64) {
+            const size_t w1 = w0 + 64 < wx.size() ? w0 + 64 : wx.size();
+            *cyc_pad += extra_cycles(std::vector<int>(wp.begin() + w0, wp.begin() + w1), esz);
+            *cyc_xor += extra_cycles(std::vector<int>(wx.begin() + w0, wx.begin() + w1), esz);
+          }
+        }
+      for (int j = 0; j < E; ++j) {
+        std::vector<int> rp, rx;
+        for (int t = 0; t < TPT; ++t) {
+          const int sx = tbs::xread_slot(xl, TPT, t, j);
+          bad += (sx != at[(size_t)(t + j * TPT)]);
+          rp.push_back(tbs::xread_slot(pad, TPT, t, j));
+          rx.push_back(sx);
+        }
+        for (size_t w0 = 0; w0 < rx.size(); w0 += 64) {
+          const size_t w1 = w0 + 64 < rx.size() ? w0 + 64 : rx.size();
+          *cyc_pad += extra_cycles(std::vector<int>(rp.begin() + w0, rp.begin() + w1), esz);
+          *cyc_xor += extra_cycles(std::vector<int>(rx.begin() + w0, rx.begin() + w1), esz);
+        }
+      }
+    }
     L *= R;
   }
   return bad;

@@ -363,7 +363,9 @@ int run_cols(tbs_plan* p, bool adjoint) {
   }
 
   tbs::ColArgs z{};
-  z.sub = 1;
+  // z lines per block: the tuned count (a divisor of the layout block) or cb
+  const int znc = p->conv_nc ? p->conv_nc : (int)cb;
+  z.sub = (int)cb / znc;
   z.in = p->Yb;
   z.out = p->Yb;
   z.tw = p->tw[2];
@@ -377,7 +379,7 @@ int run_cols(tbs_plan* p, bool adjoint) {
   z.in_s1 = z.out_s1 = my * nz * cb;
   z.in_s0 = z.out_s0 = nz * cb;
   z.nrhs = p->batch;
-  z.n1 = (int)nkb;
+  z.n1 = (int)nkb * z.sub;
   z.n0 = (int)my;
   z.cb = (int)cb;
   z.zcols = 0;
@@ -390,7 +392,7 @@ int run_cols(tbs_plan* p, bool adjoint) {
   z.mirror = 1;
   {
     ProfScope ps(p, PK_COL_CONV);
-    TBS_LAUNCH(p, tbs::launch_col_pass(p->fp64, (int)p->M[2], (int)cb, z, p->stream));
+    TBS_LAUNCH(p, tbs::launch_col_pass(p->fp64, (int)p->M[2], znc, z, p->stream));
   }
 
   tbs::ColArgs iv = y;
@@ -1752,11 +1754,55 @@ int tbs_plan_autotune(tbs_plan* p, int* row_nr_out, int* conv_nc_out) {
       }
       tune_store(key, {p->row_nr, p->conv_nc});
     }
+  } else {
+    // 3D: z lines per block of the z convolution (its y passes and the x row
+    // pass have one compiled shape at these lengths)
+    const std::string key = "plan3 " + device_tag(p->device) + " " + (p->fp64 ? "c128" : "c64") + " N" +
+                            std::to_string(p->N[0]) + "x" + std::to_string(p->N[1]) + "x" +
+                            std::to_string(p->N[2]) + " M" + std::to_string(p->M[0]) + "x" +
+                            std::to_string(p->M[1]) + "x" + std::to_string(p->M[2]) + " B" +
+                            std::to_string(p->batch);
+    int cand[8];
+    const int n = tbs::conv_nc_candidates((int)p->M[2], p->fp64, p->cb, cand);
+    std::vector<int> v;
+    if (tune_lookup(key, &v) && v.size() == 1 && in_list(v[0], cand, n)) {
+      p->conv_nc = v[0];
+    } else if (n > 1) {
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        (void)hipGetLastError();
+        if (e0) (void)hipEventDestroy(e0);
+        return hip_fail(p, hipErrorOutOfMemory, "events");
+      }
+      double best = 1e30;
+      int pick = cand[0];
+      int rc = TBS_OK;
+      for (int i = 0; i < n && !rc; ++i) {
+        p->conv_nc = cand[i];
+        for (int w = 0; w < 2 && !rc; ++w) rc = run_cols(p, false);
+        (void)hipEventRecord(e0, p->stream);
+        for (int r = 0; r < 3 && !rc; ++r) rc = run_cols(p, false);
+        (void)hipEventRecord(e1, p->stream);
+        if (rc || hipEventSynchronize(e1) != hipSuccess) break;
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best) {
+          best = ms;
+          pick = cand[i];
+        }
+      }
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      p->conv_nc = rc ? 0 : pick;
+      if (rc) return rc;
+      tune_store(key, {pick});
+    }
   }
   if (row_nr_out) *row_nr_out = p->row_nr ? p->row_nr : tbs::row_rows_per_block((int)p->M[0], p->fp64);
   if (conv_nc_out) {
     int nc = 0;
     if (p->ndim == 2) (void)make_conv2d_args(p, false, &nc);
+    else nc = p->conv_nc ? p->conv_nc : p->cb;
     *conv_nc_out = nc;
   }
   return TBS_OK;

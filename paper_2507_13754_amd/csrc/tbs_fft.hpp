@@ -362,6 +362,98 @@ __host__ __device__ constexpr int write_slot(int TPT, int L, int R, int t, int q
              : lpad(stage_out_index(t + q * TPT, L, R, r));
 }
 
+// XOR layout of one exchange (the writes of a stage of radix R and span L and
+// the reads of the next stage), used where L and R are powers of two.  LDS
+// serves G = 128 / (bytes per element) lanes of one instruction per cycle (32
+// banks of 4 bytes), conflict-free when their element indices differ mod G.
+// The reads touch G consecutive indices: distinct mod G under any XOR of the
+// low bits by a value taken from bits above them.  The writes touch G/L runs
+// of L consecutive indices at stride L R (or, for L R < G, R windows of G
+// indices that repeat the same residues): flipping bits [log2 L, log2 L + nb)
+// by the run (window) number read from bits [s, s + nb) spreads them over
+// all banks.  The padded layout above leaves 2- to 4-way conflicts on the
+// radix-4 stages of 3 * 2^a and 5 * 2^a lines (L = 4) and on all stages with
+// L < 16 of 8- and 16-byte elements where L R > 16.  Indices stay inside
+// their aligned block of G (M a multiple of G), so the line needs M slots.
+#ifndef TBS_LDS_SWIZZLE
+#define TBS_LDS_SWIZZLE 1
+#endif
+struct Swz {
+  int s, nb, tb;  // source bit, width, target bit; nb < 0: padded layout
+};
+__host__ __device__ constexpr bool pow2_int(int x) { return x > 0 && (x & (x - 1)) == 0; }
+__host__ __device__ constexpr int log2_int(int x) {
+  int n = 0;
+  while ((1 << n) < x) ++n;
+  return n;
+}
+// Whether the padded layout serves the writes of stage (L, R) and the reads
+// of the next stage in the first wave without bank conflicts (butterfly 0
+// and register 0: the others are the same patterns shifted by multiples of
+// 16 elements).  Elements of 128 / G bytes cover 32 / G consecutive banks.
+__host__ __device__ constexpr bool pad_group_ok(int a, int b, int words) {
+  for (int d = 0; d < words; ++d)
+    for (int e = 0; e < words; ++e)
+      if ((a * words + d) % 32 == (b * words + e) % 32 && a != b) return false;
+  return true;
+}
+__host__ __device__ constexpr bool pad_conflict_free(int TPT, int L, int R, int G) {
+  const int words = 32 / G;
+  const int lanes = TPT < 64 ? TPT : 64;
+  for (int g0 = 0; g0 < lanes; g0 += G)
+    for (int i = g0 + 1; i < g0 + G && i < lanes; ++i)
+      for (int k = g0; k < i; ++k) {
+        if (!pad_group_ok(read_slot(TPT, i, 0), read_slot(TPT, k, 0), words)) return false;
+        for (int r = 0; r < R; ++r)
+          if (!pad_group_ok(write_slot(TPT, L, R, i, 0, r), write_slot(TPT, L, R, k, 0, r), words))
+            return false;
+      }
+  return true;
+}
+// The layout of one exchange: the padded one where it is conflict-free (its
+// slots fold into the instructions' offsets), else the XOR layout.
+__host__ __device__ constexpr Swz swz_of(int M, int TPT, int L, int R, int G) {
+  if (!TBS_LDS_SWIZZLE || !pow2_int(L) || !pow2_int(R) || M % G != 0 ||
+      pad_conflict_free(TPT, L, R, G))
+    return Swz{0, -1, 0};
+  if (L >= G) return Swz{0, 0, log2_int(L)};  // runs of G or more: plain indices
+  return L * R >= G ? Swz{log2_int(L * R), log2_int(G / L), log2_int(L)}
+                    : Swz{log2_int(G), log2_int(R), log2_int(L)};
+}
+__host__ __device__ constexpr int swz_apply(int e, Swz p) {
+  return e ^ (((e >> p.s) & ((1 << p.nb) - 1)) << p.tb);
+}
+// Reads of the next stage: element t + j TPT.  With TPT a multiple of
+// 2^(s + nb) the XOR mask does not depend on j (one base, constant offsets);
+// with TPT a divisor of 2^s (t >> s == 0) and a multiple of 2^(tb + nb) it
+// depends on j alone: 2^nb bases t ^ (c << tb), constant offsets.
+__host__ __device__ constexpr int xread_slot(Swz p, int TPT, int t, int j) {
+  return p.nb < 0 ? read_slot(TPT, t, j)
+         : (TPT % (1 << (p.s + p.nb)) == 0) ? swz_apply(t, p) + j * TPT
+         : ((1 << p.s) % TPT == 0 && TPT % (1 << (p.tb + p.nb)) == 0)
+             ? (t ^ ((((j * TPT) >> p.s) & ((1 << p.nb) - 1)) << p.tb)) + j * TPT
+             : swz_apply(t + j * TPT, p);
+}
+// Writes: output r of butterfly t + q TPT.  base = (t / L) L R + t mod L has
+// zeros in bits [log2 L, log2 L R), and the mask bits come from above s >=
+// log2 L R, so the slot is base + ((r ^ mask) << log2 L) + q TPT R when TPT
+// is a multiple of L and TPT R one of 2^(s + nb).  Splitting r = rh 2^nb +
+// rl, that is base + ((rl ^ mask) << tb) + (rh << (tb + nb)) + q TPT R:
+// 2^nb bases per thread, the rest constant offsets.
+__host__ __device__ constexpr bool xwrite_fast(Swz p, int TPT, int L, int R) {
+  return p.nb >= 0 && TPT % L == 0 && (TPT * R) % (1 << (p.s + p.nb)) == 0;
+}
+__host__ __device__ constexpr int xwrite_base(Swz p, int L, int R, int t, int rl) {
+  const int base = (t / L) * L * R + t % L;
+  return base + ((rl ^ ((base >> p.s) & ((1 << p.nb) - 1))) << p.tb);
+}
+__host__ __device__ constexpr int xwrite_slot(Swz p, int TPT, int L, int R, int t, int q, int r) {
+  if (p.nb < 0) return write_slot(TPT, L, R, t, q, r);
+  if (xwrite_fast(p, TPT, L, R))
+    return xwrite_base(p, L, R, t, r & ((1 << p.nb) - 1)) + ((r >> p.nb) << (p.tb + p.nb)) + q * TPT * R;
+  return swz_apply(stage_out_index(t + q * TPT, L, R, r), p);
+}
+
 // One Stockham stage S and the exchange to stage S+1 (recursively).
 // SPLIT: exchange real and imaginary parts in two rounds through a scalar LDS
 // buffer of M (+pad) values, halving the LDS a line needs (four barriers per
@@ -384,6 +476,7 @@ __device__ __forceinline__ void fft_stages(cx<T> (&v)[E], void* __restrict__ shv
   // index t + j' TPT with j' fixed by (q, r): the reader is the writing thread
   // itself, so the exchange is a register renaming (no LDS, no barrier).
   constexpr bool LOCAL = stage_is_local(M, E, S);
+  constexpr Swz XL = swz_of(M, TPT, L, R, 128 / (SPLIT ? (int)sizeof(T) : 2 * (int)sizeof(T)));
   cx<T> w[LOCAL ? E : 1];
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
@@ -410,7 +503,7 @@ __device__ __forceinline__ void fft_stages(cx<T> (&v)[E], void* __restrict__ shv
     } else {
       cx<T>* sh = (cx<T>*)shv;
 #pragma unroll
-      for (int r = 0; r < R; ++r) sh[write_slot(TPT, L, R, t, q, r)] = a[r];
+      for (int r = 0; r < R; ++r) sh[xwrite_slot(XL, TPT, L, R, t, q, r)] = a[r];
     }
   }
   if constexpr (LOCAL) {
@@ -423,26 +516,26 @@ __device__ __forceinline__ void fft_stages(cx<T> (&v)[E], void* __restrict__ shv
 #pragma unroll
       for (int q = 0; q < NB; ++q) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) sh[write_slot(TPT, L, R, t, q, r)] = v[q + r * NB].x;
+        for (int r = 0; r < R; ++r) sh[xwrite_slot(XL, TPT, L, R, t, q, r)] = v[q + r * NB].x;
       }
       __syncthreads();
 #pragma unroll
-      for (int j = 0; j < E; ++j) v[j].x = sh[read_slot(TPT, t, j)];
+      for (int j = 0; j < E; ++j) v[j].x = sh[xread_slot(XL, TPT, t, j)];
       __syncthreads();
 #pragma unroll
       for (int q = 0; q < NB; ++q) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) sh[write_slot(TPT, L, R, t, q, r)] = v[q + r * NB].y;
+        for (int r = 0; r < R; ++r) sh[xwrite_slot(XL, TPT, L, R, t, q, r)] = v[q + r * NB].y;
       }
       __syncthreads();
 #pragma unroll
-      for (int j = 0; j < E; ++j) v[j].y = sh[read_slot(TPT, t, j)];
+      for (int j = 0; j < E; ++j) v[j].y = sh[xread_slot(XL, TPT, t, j)];
       __syncthreads();
     } else {
       cx<T>* sh = (cx<T>*)shv;
       __syncthreads();
 #pragma unroll
-      for (int j = 0; j < E; ++j) v[j] = sh[read_slot(TPT, t, j)];
+      for (int j = 0; j < E; ++j) v[j] = sh[xread_slot(XL, TPT, t, j)];
       __syncthreads();
     }
     fft_stages<T, M, E, INV, SPLIT, TWC, S + 1>(v, shv, tw, twc, t);

@@ -77,6 +77,30 @@ def test_lds_slot_closed_forms(hc, M, E):
     assert hc.tbs_hostcheck_slots(M, E) == 0
 
 
+LDS_CASES = [(M, E) for M, E in [(16, 4), (32, 4), (64, 4), (128, 8), (256, 8), (512, 8), (1024, 16),
+                                  (2048, 16), (4096, 16), (48, 12), (96, 12), (192, 12), (384, 12), (768, 12),
+                                  (1536, 12), (3072, 12), (80, 20), (160, 20), (320, 20), (640, 20),
+                                  (1280, 20), (2560, 20), (2560, 40), (1536, 24)]]
+
+
+@pytest.mark.parametrize("esz", [4, 8, 16])
+@pytest.mark.parametrize("M,E", LDS_CASES)
+def test_lds_xor_layout(hc, M, E, esz):
+    """The XOR layout of the LDS exchanges (4-byte split halves, FP32 and FP64
+    complex values): the slots the device computes are the layout of the
+    indices they stand for, one element per slot, every read finds its
+    element; under the 32-bank model no lane group of a line of 128+ values
+    waits on a bank conflict, and no length does worse than with the padded
+    layout (which conflicts on the radix-4 stages of 3*2^a and 5*2^a lines)."""
+    pad, xor = ctypes.c_int(), ctypes.c_int()
+    assert hc.tbs_hostcheck_xslots(M, E, esz, ctypes.byref(pad), ctypes.byref(xor)) == 0
+    assert xor.value <= pad.value
+    if M >= 128:
+        assert xor.value == 0
+    if esz == 8 and (M, E) in ((768, 12), (1536, 12), (640, 20), (1280, 20), (2560, 20)):
+        assert pad.value > 0
+
+
 @pytest.mark.parametrize("M,E", [(16, 4), (64, 4), (512, 8), (1024, 16), (2048, 16), (4096, 16), (48, 12),
                                  (96, 12), (768, 12), (1536, 12), (3072, 12), (80, 20), (640, 20),
                                  (1280, 20), (2560, 20), (2560, 40), (1536, 24)])

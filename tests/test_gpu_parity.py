@@ -321,3 +321,25 @@ def test_autotuned_plan_is_bitwise_identical(dev, shape):
     assert np.allclose(r0, r1, rtol=1e-13, atol=0)
     base.close()
     tuned.close()
+
+
+@pytest.mark.parametrize("shape", [(70, 50, 60), (130, 40, 34)])
+def test_autotuned_3d_plan_is_bitwise_identical(dev, shape):
+    """3D plans tune the z lines per block of the z convolution; the field is
+    bitwise equal to the default shape's and the choice is reported."""
+    import paper_2507_13754_amd as tbs
+    dx, k0, V, s = small_case(shape, seed=41)
+    s = s[:1]
+    L = 4
+    base = tbs.Plan(shape, dx, k0, dtype=torch.complex64).tabulate()
+    tuned = tbs.Plan(shape, dx, k0, dtype=torch.complex64).tabulate()
+    _, nc = tuned.autotune()
+    assert nc in (1, 2, 4)
+    sd = torch.from_numpy(s).to(dev, torch.complex64)
+    Vd = torch.from_numpy(V).to(dev, torch.complex64)
+    p0, r0 = base.solve(sd, Vd, L, residual=True)
+    p1, r1 = tuned.solve(sd, Vd, L, residual=True)
+    assert torch.equal(p0, p1)
+    assert np.allclose(r0, r1, rtol=1e-13, atol=0)
+    base.close()
+    tuned.close()
