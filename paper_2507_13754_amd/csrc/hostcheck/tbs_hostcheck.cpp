@@ -149,25 +149,29 @@ extern "C" int tbs_hostcheck_slots(int M, int E) {
   return bad;
 }
 
-// The XOR exchange layouts (swz_of / xwrite_slot / xread_slot) for LDS
-// elements of esz bytes: the closed forms equal the layout applied to the
-// defining index, the write slots of a stage are distinct and inside the
-// line's slots, and every read finds the element it stands for.  Bank model
-// of gfx950's LDS: 32 banks of 4 bytes, 128 / esz lanes of one instruction
-// served per cycle, an access of esz bytes covering esz / 4 consecutive
-// banks; lanes of one group on the same bank at different addresses cost
-// one extra cycle each.  *cyc_pad / *cyc_xor: the extra cycles of all the
-// exchanges of one line (waves of 64 lanes) with the padded layout and with
-// the layout the device uses.  Returns the number of mismatches.
+// The LDS exchange layouts of a pass block of NL lines (LDS elements of esz
+// bytes, one buffer of lds_len slots per line) whose lanes take the lines as
+// the passes do: kind 0 (column pass) lane l -> line l mod NL, value index
+// l / NL; kind 1 (row pass, 4-value column blocks) lane l -> line (l / 4) mod
+// NL, value index (l / (4 NL)) 4 + l mod 4.  "new" is the layout the passes
+// use (swz_of), "pad" the padded layout throughout.  Checks for the new
+// layout: the closed-form slots equal the layout of the indices they stand
+// for, every write slot is inside the line's buffer and taken once per stage,
+// every read finds the element it stands for.  Bank model of gfx950's LDS: 32
+// banks of 4 bytes, 128 / esz lanes of one instruction served per cycle, an
+// access of esz bytes covering esz / 4 consecutive banks; lanes of one group
+// on one bank at different addresses cost one extra cycle each.  *cyc_pad /
+// *cyc_new: the extra cycles of all exchanges of one block (waves of 64
+// lanes).  Returns the number of mismatches.
 namespace {
-int extra_cycles(const std::vector<int>& slot, int esz) {
+int extra_cycles(const std::vector<int>& addr, int esz) {
   const int G = 128 / esz, words = esz / 4;
   int extra = 0;
-  for (size_t g0 = 0; g0 < slot.size(); g0 += (size_t)G) {
+  for (size_t g0 = 0; g0 < addr.size(); g0 += (size_t)G) {
     std::vector<std::vector<int>> bank(32);
-    for (size_t i = g0; i < g0 + (size_t)G && i < slot.size(); ++i)
+    for (size_t i = g0; i < g0 + (size_t)G && i < addr.size(); ++i)
       for (int d = 0; d < words; ++d) {
-        const int a = slot[i] * words + d;
+        const int a = addr[i] * words + d;
         auto& b = bank[(size_t)(a % 32)];
         bool seen = false;
         for (int x : b) seen |= (x == a);
@@ -181,55 +185,71 @@ int extra_cycles(const std::vector<int>& slot, int esz) {
 }
 }  // namespace
 
-extern "C" int tbs_hostcheck_xslots(int M, int E, int esz, int* cyc_pad, int* cyc_xor) {
+extern "C" int tbs_hostcheck_xslots(int M, int E, int esz, int NL, int kind, int* cyc_pad, int* cyc_new) {
   const tbs::Stages st = tbs::make_stages(M, E);
-  if (st.n <= 0 || M % E || (esz != 4 && esz != 8 && esz != 16)) return -1;
+  if (st.n <= 0 || M % E || (esz != 4 && esz != 8 && esz != 16) || NL < 1 || (kind != 0 && kind != 1))
+    return -1;
   const int TPT = M / E;
-  const int len = tbs::lds_len(M, 1, esz);
+  if (kind == 1 && TPT % 4) return -1;
+  const int G = 128 / esz;
+  const int LDP = tbs::lds_len(M, NL, esz);
+  const int len_new = NL * LDP;
+  const int nth = NL * TPT;
+  std::vector<int> lane_line((size_t)nth), lane_t((size_t)nth);
+  for (int l = 0; l < nth; ++l) {
+    lane_line[(size_t)l] = kind == 0 ? l % NL : (l / 4) % NL;
+    lane_t[(size_t)l] = kind == 0 ? l / NL : (l / (4 * NL)) * 4 + l % 4;
+  }
   int bad = 0;
   *cyc_pad = 0;
-  *cyc_xor = 0;
+  *cyc_new = 0;
+  auto tally = [&](const std::vector<int>& ap, const std::vector<int>& an) {
+    for (size_t w0 = 0; w0 < ap.size(); w0 += 64) {
+      const size_t w1 = w0 + 64 < ap.size() ? w0 + 64 : ap.size();
+      *cyc_pad += extra_cycles(std::vector<int>(ap.begin() + w0, ap.begin() + w1), esz);
+      *cyc_new += extra_cycles(std::vector<int>(an.begin() + w0, an.begin() + w1), esz);
+    }
+  };
+  const tbs::Swz pad{0, -1, 0};
   int L = 1;
   for (int S = 0; S + 1 < st.n; ++S) {
     const int R = st.r[S];
     if (!tbs::stage_is_local(M, E, S)) {
-      const tbs::Swz xl = tbs::swz_of(M, TPT, L, R, 128 / esz);
-      const tbs::Swz pad{0, -1, 0};
-      std::vector<int> at((size_t)M, -1);   // element -> slot
-      std::vector<int> owner((size_t)len, -1);
+      const tbs::Swz xl = tbs::swz_of(M, TPT, L, R, G);
+      std::vector<int> at((size_t)NL * M, -1);  // (line, element) -> buffer slot
+      std::vector<int> owner((size_t)len_new, -1);
       for (int q = 0; q < E / R; ++q)
         for (int r = 0; r < R; ++r) {
-          std::vector<int> wp, wx;
-          for (int t = 0; t < TPT; ++t) {
+          std::vector<int> ap, an;
+          for (int l = 0; l < nth; ++l) {
+            const int ln = lane_line[(size_t)l], t = lane_t[(size_t)l];
             const int e = tbs::stage_out_index(t + q * TPT, L, R, r);
             const int sx = tbs::xwrite_slot(xl, TPT, L, R, t, q, r);
-            const int want = xl.nb < 0 ? tbs::lpad(e) : tbs::swz_apply(e, xl);
+            const int want = xl.nb < 0 ? tbs::write_slot(TPT, L, R, t, q, r) : tbs::swz_apply(e, xl);
             bad += sx != want;
-            if (sx < 0 || sx >= len || owner[(size_t)sx] >= 0) { ++bad; continue; }
-            owner[(size_t)sx] = e;
-            at[(size_t)e] = sx;
-            wp.push_back(tbs::xwrite_slot(pad, TPT, L, R, t, q, r));
-            wx.push_back(sx);
+            const int addr = ln * LDP + sx;
+            if (sx < 0 || sx >= LDP || addr >= len_new || owner[(size_t)addr] >= 0) {
+              ++bad;
+              continue;
+            }
+            owner[(size_t)addr] = e;
+            at[(size_t)ln * M + e] = addr;
+            ap.push_back(ln * LDP + tbs::xwrite_slot(pad, TPT, L, R, t, q, r));
+            an.push_back(addr);
           }
-          for (size_t w0 = 0; w0 < wx.size(); w0 += 64) {
-            const size_t w1 = w0 + 64 < wx.size() ? w0 + 64 : wx.size();
-            *cyc_pad += extra_cycles(std::vector<int>(wp.begin() + w0, wp.begin() + w1), esz);
-            *cyc_xor += extra_cycles(std::vector<int>(wx.begin() + w0, wx.begin() + w1), esz);
-          }
+          tally(ap, an);
         }
       for (int j = 0; j < E; ++j) {
-        std::vector<int> rp, rx;
-        for (int t = 0; t < TPT; ++t) {
+        std::vector<int> ap, an;
+        for (int l = 0; l < nth; ++l) {
+          const int ln = lane_line[(size_t)l], t = lane_t[(size_t)l];
           const int sx = tbs::xread_slot(xl, TPT, t, j);
-          bad += (sx != at[(size_t)(t + j * TPT)]);
-          rp.push_back(tbs::xread_slot(pad, TPT, t, j));
-          rx.push_back(sx);
+          const int addr = ln * LDP + sx;
+          bad += (addr != at[(size_t)ln * M + t + j * TPT]);
+          ap.push_back(ln * LDP + tbs::xread_slot(pad, TPT, t, j));
+          an.push_back(addr);
         }
-        for (size_t w0 = 0; w0 < rx.size(); w0 += 64) {
-          const size_t w1 = w0 + 64 < rx.size() ? w0 + 64 : rx.size();
-          *cyc_pad += extra_cycles(std::vector<int>(rp.begin() + w0, rp.begin() + w1), esz);
-          *cyc_xor += extra_cycles(std::vector<int>(rx.begin() + w0, rx.begin() + w1), esz);
-        }
+        tally(ap, an);
       }
     }
     L *= R;

@@ -83,22 +83,28 @@ LDS_CASES = [(M, E) for M, E in [(16, 4), (32, 4), (64, 4), (128, 8), (256, 8), 
                                   (1280, 20), (2560, 20), (2560, 40), (1536, 24)]]
 
 
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("NL", [1, 2, 4])
 @pytest.mark.parametrize("esz", [4, 8, 16])
 @pytest.mark.parametrize("M,E", LDS_CASES)
-def test_lds_xor_layout(hc, M, E, esz):
-    """The XOR layout of the LDS exchanges (4-byte split halves, FP32 and FP64
-    complex values): the slots the device computes are the layout of the
-    indices they stand for, one element per slot, every read finds its
-    element; under the 32-bank model no lane group of a line of 128+ values
-    waits on a bank conflict, and no length does worse than with the padded
-    layout (which conflicts on the radix-4 stages of 3*2^a and 5*2^a lines)."""
-    pad, xor = ctypes.c_int(), ctypes.c_int()
-    assert hc.tbs_hostcheck_xslots(M, E, esz, ctypes.byref(pad), ctypes.byref(xor)) == 0
-    assert xor.value <= pad.value
-    if M >= 128:
-        assert xor.value == 0
-    if esz == 8 and (M, E) in ((768, 12), (1536, 12), (640, 20), (1280, 20), (2560, 20)):
-        assert pad.value > 0
+def test_lds_exchange_layout(hc, M, E, esz, NL, kind):
+    """The LDS exchange layouts of a pass block of NL lines whose lanes take
+    the lines as the column pass (kind 0) or the row pass (kind 1) does, for
+    4-byte split halves, FP32 and FP64 complex values: the slots the device
+    computes are the layout of the indices they stand for, one element per
+    slot, every read finds its element; under the 32-bank model a block of
+    one line of 128+ values waits on no bank conflict, where the padded
+    layout conflicts on the radix-4 stages of 3*2^a and 5*2^a lines."""
+    if kind == 1 and (M // E) % 4:
+        pytest.skip("row passes need 4-value column blocks")
+    pad, new = ctypes.c_int(), ctypes.c_int()
+    assert hc.tbs_hostcheck_xslots(M, E, esz, NL, kind, ctypes.byref(pad), ctypes.byref(new)) == 0
+    if NL == 1:
+        assert new.value <= pad.value
+        if M >= 128:
+            assert new.value == 0
+        if esz == 8 and (M, E) in ((768, 12), (1536, 12), (640, 20), (1280, 20), (2560, 20)):
+            assert pad.value > 0
 
 
 @pytest.mark.parametrize("M,E", [(16, 4), (64, 4), (512, 8), (1024, 16), (2048, 16), (4096, 16), (48, 12),
