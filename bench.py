@@ -185,12 +185,11 @@ def cpu_info():
 # ------------------------------------------------------- counter records ---
 
 def read_counters(kernel_re: str):
-    """HBM traffic per term of the kernel whose name matches kernel_re, from
-    the counter summary under profiles/ (two rocprofv3 --pmc runs, FETCH_SIZE
-    then WRITE_SIZE, scaled by a plain copy's readings, taken with the batch
-    in one launch chain: one dispatch of each kernel per term covers all grids
-    of its length); None when the kernel sources changed since the counters
-    were taken."""
+    """HBM traffic per term of the kernel whose name matches kernel_re (all
+    its dispatches of one term, every set of tiles), from the counter summary
+    under profiles/ (two rocprofv3 --pmc runs, FETCH_SIZE then WRITE_SIZE,
+    scaled by a plain copy's readings); None when the kernel sources or the
+    batch schedule changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "counters_broadband.json")
     if not os.path.exists(path):
         return None
@@ -201,8 +200,8 @@ def read_counters(kernel_re: str):
     if d.get("sources_sha256_16") != kernel_sources_hash():
         return None
     for name, v in d.get("kernels", {}).items():
-        if re.search(kernel_re, name):
-            return v["traffic_bytes_per_launch"]
+        if re.search(kernel_re, name) and "traffic_bytes_per_term" in v:
+            return v["traffic_bytes_per_term"]
     return None
 
 
@@ -274,19 +273,24 @@ def run_broadband(dev, steps: int, warmup: int, fp64: bool, tune: bool):
             if e["launches"] == 0:
                 continue
             a = agg.setdefault((e["kind"], e["length"], e["shape"]),
-                               {"members": [], "ms": 0.0, "launches": 0, "groups": 0})
+                               {"members": [], "member_rhs": [], "ms": 0.0, "launches": 0, "groups": 0})
             a["members"] += e["members"]
+            a["member_rhs"] += e["member_rhs"]
             a["ms"] += e["ms"]
             a["launches"] += e["launches"]
             a["groups"] += 1
         entries = []
         for (kind, length, shape), e in agg.items():
-            bl = sum(pass_bytes_2d(kind, geo[i][0], geo[i][1], geo[i][2], fp) for i in e["members"])
-            blc = sum(pass_bytes_2d(kind, geo[i][0], geo[i][1], geo[i][2], fp, geo[i][3], geo[i][4])
-                      for i in e["members"])
+            # a tile of r of a grid's B right-hand sides carries r / B of that
+            # grid's algorithmic bytes (potential and spectrum once per grid)
+            tiles = list(zip(e["members"], e["member_rhs"]))
+            bl = sum(pass_bytes_2d(kind, geo[i][0], geo[i][1], geo[i][2], fp) * r / geo[i][2] for i, r in tiles)
+            blc = sum(pass_bytes_2d(kind, geo[i][0], geo[i][1], geo[i][2], fp, geo[i][3], geo[i][4]) * r / geo[i][2]
+                      for i, r in tiles)
             per_term = e["launches"] / e["groups"] / nprof         # launches of one group per step
             t_term = e["ms"] / nprof / per_term                   # all groups of this kernel, one term
-            entries.append({"kind": kind, "length": length, "shape": shape, "grids": len(e["members"]),
+            entries.append({"kind": kind, "length": length, "shape": shape, "grids": len(set(e["members"])),
+                            "tiles": len(tiles), "rhs": sum(r for _, r in tiles),
                             "launches_per_step": e["launches"] / nprof, "grouped_launches_per_term": e["groups"],
                             "avg_launch_ms": e["ms"] / e["launches"], "ms_per_term": t_term,
                             "ms_per_step": e["ms"] / nprof, "alg_bytes_per_term": bl,
@@ -309,8 +313,8 @@ def run_broadband(dev, steps: int, warmup: int, fp64: bool, tune: bool):
             "frac": dom["GBps"] / HBM_PEAK_GBS,
             "traffic": traffic,
             "kernel": (f"{group_kernel_name(dom)}: {dom['kind']}, FFT length {dom['length']}, "
-                       f"{dom['grids']} grids x {geo[0][2]} RHS in {dom['grouped_launches_per_term']} "
-                       "grouped launches per term"),
+                       f"{dom['grids']} grids ({dom['rhs']} RHS in {dom['tiles']} tiles) in "
+                       f"{dom['grouped_launches_per_term']} grouped launches per term"),
             "alg_bytes_per_term": dom["alg_bytes_per_term"], "ms_per_term": dom["ms_per_term"],
             "avg_launch_ms": dom["avg_launch_ms"], "launches_per_step": dom["launches_per_step"]}
     out = {"r32": r32, "roofline": roof, "L": L, "geo": geo}

@@ -348,11 +348,19 @@ typedef struct tbs_batch tbs_batch;
 /* Group plans (e.g. one per frequency of a broadband pulse, each with its own
  * grid, k0 and B right-hand sides) for joint solves.  All plans must be 2D,
  * share the dtype and be tabulated; the batch queues its work on the first
- * plan's stream.  The plans must outlive the batch.  Passes of grids whose
+ * plan's stream.  The plans must outlive the batch.  Schedule: each plan's
+ * right-hand sides are cut into tiles of at most TBS_BATCH_TILE_RHS (default
+ * 4), and consecutive tiles (in plan order) are packed into sets whose working
+ * set (intermediate, sum, compensation, potential and spectrum of one term)
+ * stays within TBS_BATCH_CACHE_MB megabytes (default 256, sized for the
+ * 256 MB last-level cache; 0 runs all plans as one set of whole plans).  The
+ * sets run one after the other, each its whole series, so that a set's data
+ * stays cache-resident between passes.  Within a set, passes of tiles whose
  * padded lengths coincide run in one grouped kernel launch per term.  With
- * the environment variable TBS_BATCH_CHAINS=2 (and two or more plans) the work
- * is split in two halves of equal size whose pass sequences run on two
- * streams, one pass apart; results are bitwise the same. */
+ * the environment variable TBS_BATCH_CHAINS=2 (and two or more plans) the
+ * whole plans are split in two halves of equal size whose pass sequences run
+ * on two streams, one pass apart (one set).  Results are bitwise the same for
+ * every schedule. */
 int tbs_batch_create(tbs_batch **out, tbs_plan *const *plans, int nplans);
 
 /* The L-term series of every plan in the batch (the tbs_solve contract per
@@ -392,16 +400,20 @@ int tbs_batch_profile_enable(tbs_batch *batch, int enable);
 /* Synchronise the batch stream and return the timing since the last read, per
  * entry e < *nentries: one entry per grouped launch kind, i.e. three per row
  * group (kind[e] = 0 first row pass, 1 middle row passes, 2 last row pass) and
- * one per column group (kind[e] = 3 column convolution).  length[e]: the FFT
- * length of the group's lines; shape[e]: lines per block (rows per row-pass
- * block, columns per column-pass block); launches[e]: launches timed; ms[e]: summed
- * event time in ms; the group's plans (indices into the tbs_batch_create
- * array) are members[first[e] .. first[e+1]).  cap: capacity of kind,
- * length, shape, launches and ms (first needs cap + 1; members the total count, at
- * most cap * nplans); *nentries is set even when cap is too small
- * (TBS_ERR_INVALID then, nothing else written).  Resets the counters. */
+ * one per column group (kind[e] = 3 column convolution).  A group is one set
+ * of tiles (see tbs_batch_create) and one padded length and block shape.
+ * length[e]: the FFT length of the group's lines; shape[e]: lines per block
+ * (rows per row-pass block, columns per column-pass block); launches[e]:
+ * launches timed; ms[e]: summed event time in ms; the group's tiles are
+ * members[first[e] .. first[e+1]) (the index of the tile's plan in the
+ * tbs_batch_create array) with member_rhs[...] right-hand sides each
+ * (member_rhs may be NULL).  cap: capacity of kind, length, shape, launches
+ * and ms (first needs cap + 1; members and member_rhs the total count, at most
+ * 4 x the batch's total right-hand sides); *nentries is set even when cap is
+ * too small (TBS_ERR_INVALID then, nothing else written).  Resets the
+ * counters. */
 int tbs_batch_profile_read(tbs_batch *batch, int cap, int *nentries, int *kind, int *length, int *shape,
-                           int64_t *launches, double *ms, int *first, int *members);
+                           int64_t *launches, double *ms, int *first, int *members, int *member_rhs);
 
 /* Per-pass device timing.  While enabled, every pass launch is bracketed by
  * two HIP events recorded on the plan's stream.  Pass kinds (index into the

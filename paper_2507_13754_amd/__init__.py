@@ -23,6 +23,7 @@ LIB_PATH = os.environ.get("TBS_LIBRARY", os.path.join(HERE, "libtbs.so"))
 
 TBS_C64, TBS_C128 = 0, 1
 TBS_OK = 0
+TBS_ERR_INVALID = -1
 TBS_WARN_NONFINITE, TBS_WARN_DIVERGING, TBS_WARN_NOT_CONVERGED = 1, 2, 3
 TBS_ADJ_STORE, TBS_ADJ_RECOMPUTE, TBS_ADJ_SERIES_ONLY = 0, 1, 2
 TBS_ITER_PAPER, TBS_ITER_CBS = 0, 1
@@ -113,7 +114,7 @@ def library() -> ctypes.CDLL:
         "tbs_batch_profile_read": (ctypes.c_int, [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                                   ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                                   ctypes.POINTER(ctypes.c_int), i64p, dp, ctypes.POINTER(ctypes.c_int),
-                                                  ctypes.POINTER(ctypes.c_int)]),
+                                                  ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
         "tbs_batch_last_error": (ctypes.c_char_p, [vp]),
         "tbs_last_error": (ctypes.c_char_p, [vp]),
         "tbs_green_periodic": (ctypes.c_int, [vp, ctypes.c_double, vp]),
@@ -572,24 +573,32 @@ class Batch:
 
     def profile_read(self):
         """Timing since the last read: a list of dicts (kind name, FFT length,
-        launches, summed ms, member plan indices), one per grouped launch kind."""
+        launches, summed ms, member tiles as plan indices with their
+        right-hand-side counts), one per grouped launch kind of every set."""
         L = library()
         ne = ctypes.c_int()
-        cap = 4 * len(self.plans) + 8
         ci = ctypes.c_int
-        kind, length, shape, first = (ci * cap)(), (ci * cap)(), (ci * cap)(), (ci * (cap + 1))()
-        members = (ci * (cap * len(self.plans)))()
-        launches = (ctypes.c_int64 * cap)()
-        ms = (ctypes.c_double * cap)()
-        rc = L.tbs_batch_profile_read(self._h, cap, ctypes.byref(ne), kind, length, shape, launches, ms, first,
-                                      members)
+        cap = 0
+        while True:
+            kind, length, shape, first = (ci * max(cap, 1))(), (ci * max(cap, 1))(), (ci * max(cap, 1))(), (ci * (cap + 1))()
+            mcap = 4 * sum(p.batch for p in self.plans) + 8
+            members, mrhs = (ci * mcap)(), (ci * mcap)()
+            launches = (ctypes.c_int64 * max(cap, 1))()
+            ms = (ctypes.c_double * max(cap, 1))()
+            rc = L.tbs_batch_profile_read(self._h, cap, ctypes.byref(ne), kind, length, shape, launches, ms, first,
+                                          members, mrhs)
+            if rc == TBS_ERR_INVALID and ne.value > cap:
+                cap = ne.value
+                continue
+            break
         if rc != TBS_OK:
             raise TBSError(rc, f"tbs_batch_profile_read: {L.tbs_batch_last_error(self._h).decode()}")
         out = []
         for e in range(ne.value):
             out.append({"kind": PASS_KINDS[kind[e]], "length": int(length[e]), "shape": int(shape[e]),
-                        "launches": int(launches[e]),
-                        "ms": float(ms[e]), "members": [int(members[i]) for i in range(first[e], first[e + 1])]})
+                        "launches": int(launches[e]), "ms": float(ms[e]),
+                        "members": [int(members[i]) for i in range(first[e], first[e + 1])],
+                        "member_rhs": [int(mrhs[i]) for i in range(first[e], first[e + 1])]})
         return out
 
     def close(self):

@@ -657,21 +657,31 @@ struct tbs_batch {
   int chains = 1;
   hipStream_t stream2 = nullptr;
   hipEvent_t ev_lag = nullptr, ev_join = nullptr;
+  // Tiles: a plan's right-hand sides [r0, r0 + nrhs).  Sets: tiles whose
+  // working set (intermediate, sum, compensation, potential, spectrum) fits
+  // the device's last-level cache together; the series runs set by set (all
+  // terms of one set, then the next), so that each set's data stays in the
+  // 256 MB Infinity Cache between passes instead of streaming through HBM.
+  struct Tile {
+    int plan = 0, r0 = 0, nrhs = 0, set = 0;
+  };
+  std::vector<Tile> tiles;
+  int nsets = 1;
   struct Group {
-    int chain = 0;
+    int chain = 0, set = 0;
     int M = 0, cb = 4, nc = 0, nr = 0;
-    std::vector<int> members;  // plan indices
+    std::vector<int> members;  // tile indices
     int first = 0;             // index of the first member in the descriptor order
     int starts_off = 0;        // offset of this group's starts array
     int total = 0;             // blocks of one grouped launch
   };
   std::vector<Group> rgroups, cgroups;
-  std::vector<int> rpos, cpos;   // plan -> position in the row / column descriptor order
+  std::vector<int> rpos, cpos;   // tile -> position in the row / column descriptor order
   std::vector<int> chain_of;     // plan -> chain
   // device tables
-  void* d_row = nullptr;         // RowArgs [L+1][nplans]
+  void* d_row = nullptr;         // RowArgs [L+1][ntiles]
   size_t d_row_bytes = 0;
-  void* d_col = nullptr;         // ColArgs [nplans]
+  void* d_col = nullptr;         // ColArgs [ntiles]
   void* d_starts = nullptr;      // int
   size_t d_starts_bytes = 0;
   // descriptor tables and the arguments they were built for; the recorded graph
@@ -715,21 +725,68 @@ void batch_drop_graph(tbs_batch* b) {
   b->key_L = 0;
 }
 
-// Group the batch's plans by padded length and block shape (rows: M_x and rows
-// per block; columns: M_y, layout block and columns per block) and upload the
-// block offsets of every group; called again after the shapes change.
-int batch_group(tbs_batch* b) {
+// Working set of a tile of nrhs right-hand sides of plan p (bytes the passes
+// of one term touch): intermediate, sum and compensation per right-hand side,
+// the potential and the folded spectrum once.
+double tile_bytes(const tbs_plan* p, int nrhs) {
+  const double P = (double)p->P, esz = (double)p->esz;
+  return nrhs * ((double)p->N[1] * p->M[0] * esz + P * (esz + (p->fp64 ? 0.0 : 4.0))) + P * esz +
+         (double)(p->M[0] / 2 + 1) * (p->M[1] / 2 + 1) * esz;
+}
+
+// Split the plans into tiles of at most TBS_BATCH_TILE_RHS right-hand sides
+// (default 4) and pack consecutive tiles into sets of at most
+// TBS_BATCH_CACHE_MB megabytes of working set (default 256; 0: one set of
+// whole plans).  Two launch chains only run with a single set.
+void batch_tile(tbs_batch* b) {
   const int nplans = (int)b->plans.size();
+  double cap = 256e6;
+  int trhs = 4;
+  if (const char* e = std::getenv("TBS_BATCH_CACHE_MB")) cap = std::atof(e) * 1e6;
+  if (const char* e = std::getenv("TBS_BATCH_TILE_RHS")) trhs = std::max(1, std::atoi(e));
+  b->tiles.clear();
+  if (!(cap > 0) || b->chains == 2) {
+    for (int i = 0; i < nplans; ++i) b->tiles.push_back({i, 0, b->plans[i]->batch, 0});
+    b->nsets = 1;
+    return;
+  }
+  int set = 0;
+  double acc = 0.0;
+  bool empty = true;
+  for (int i = 0; i < nplans; ++i) {
+    const tbs_plan* p = b->plans[i];
+    for (int r0 = 0; r0 < p->batch; r0 += trhs) {
+      const int nr = std::min(trhs, p->batch - r0);
+      const double w = tile_bytes(p, nr);
+      if (!empty && acc + w > cap) {
+        ++set;
+        acc = 0.0;
+      }
+      b->tiles.push_back({i, r0, nr, set});
+      acc += w;
+      empty = false;
+    }
+  }
+  b->nsets = set + 1;
+}
+
+// Group the batch's tiles by set, padded length and block shape (rows: M_x
+// and rows per block; columns: M_y, layout block and columns per block) and
+// upload the block offsets of every group; called again after the shapes
+// change.
+int batch_group(tbs_batch* b) {
+  batch_tile(b);
+  const int nt = (int)b->tiles.size();
   b->rgroups.clear();
   b->cgroups.clear();
-  // group by padded length (rows: M_x; columns: M_y and the column shape)
-  b->rpos.assign(nplans, 0);
-  b->cpos.assign(nplans, 0);
-  auto find_or_add = [](std::vector<tbs_batch::Group>& gs, int chain, int M, int cb, int nc,
+  b->rpos.assign(nt, 0);
+  b->cpos.assign(nt, 0);
+  auto find_or_add = [](std::vector<tbs_batch::Group>& gs, int set, int chain, int M, int cb, int nc,
                         int nr) -> tbs_batch::Group& {
     for (auto& g : gs)
-      if (g.chain == chain && g.M == M && g.cb == cb && g.nc == nc && g.nr == nr) return g;
+      if (g.set == set && g.chain == chain && g.M == M && g.cb == cb && g.nc == nc && g.nr == nr) return g;
     gs.push_back(tbs_batch::Group());
+    gs.back().set = set;
     gs.back().chain = chain;
     gs.back().M = M;
     gs.back().cb = cb;
@@ -737,13 +794,15 @@ int batch_group(tbs_batch* b) {
     gs.back().nr = nr;
     return gs.back();
   };
-  for (int i = 0; i < nplans; ++i) {
-    tbs_plan* p = b->plans[i];
+  for (int t = 0; t < nt; ++t) {
+    const tbs_batch::Tile& tl = b->tiles[t];
+    tbs_plan* p = b->plans[tl.plan];
+    const int chain = b->chain_of[tl.plan];
     const int nr = p->row_nr ? p->row_nr : tbs::row_rows_per_block((int)p->M[0], p->fp64);
-    find_or_add(b->rgroups, b->chain_of[i], (int)p->M[0], p->cb, 0, nr).members.push_back(i);
+    find_or_add(b->rgroups, tl.set, chain, (int)p->M[0], p->cb, 0, nr).members.push_back(t);
     int nc = 0;
     (void)make_conv2d_args(p, false, &nc);
-    find_or_add(b->cgroups, b->chain_of[i], (int)p->M[1], p->cb, nc, 0).members.push_back(i);
+    find_or_add(b->cgroups, tl.set, chain, (int)p->M[1], p->cb, nc, 0).members.push_back(t);
   }
   std::vector<int> starts;
   int pos = 0;
@@ -751,10 +810,10 @@ int batch_group(tbs_batch* b) {
     g.first = pos;
     g.starts_off = (int)starts.size();
     int acc = 0;
-    for (int i : g.members) {
-      b->rpos[i] = pos++;
+    for (int t : g.members) {
+      b->rpos[t] = pos++;
       starts.push_back(acc);
-      acc += row_blocks(b->plans[i]) * b->plans[i]->batch;
+      acc += row_blocks(b->plans[b->tiles[t].plan]) * b->tiles[t].nrhs;
     }
     g.total = acc;
   }
@@ -763,12 +822,12 @@ int batch_group(tbs_batch* b) {
     g.first = pos;
     g.starts_off = (int)starts.size();
     int acc = 0;
-    for (int i : g.members) {
-      b->cpos[i] = pos++;
+    for (int t : g.members) {
+      b->cpos[t] = pos++;
       starts.push_back(acc);
       int nc = 0;
-      const tbs::ColArgs c = make_conv2d_args(b->plans[i], false, &nc);
-      acc += c.nrhs * c.n1 * c.n0;
+      const tbs::ColArgs c = make_conv2d_args(b->plans[b->tiles[t].plan], false, &nc);
+      acc += b->tiles[t].nrhs * c.n1 * c.n0;
     }
     g.total = acc;
   }
@@ -806,27 +865,27 @@ hipEvent_t batch_prof_begin(tbs_batch* b, int e, hipStream_t s) {
 // second runs on stream2, forked from the batch stream after the first
 // chain's first row pass and joined back at the end.
 int batch_enqueue(tbs_batch* b, int L) {
-  const int np = (int)b->plans.size();
+  const int nt = (int)b->tiles.size();
   const tbs::RowArgs* drow = (const tbs::RowArgs*)b->d_row;
   const tbs::ColArgs* dcol = (const tbs::ColArgs*)b->d_col;
   const int* dst = (const int*)b->d_starts;
   const int nrg = (int)b->rgroups.size();
-  auto rows = [&](int chain, int n, hipStream_t s) -> int {
+  auto rows = [&](int chain, int set, int n, hipStream_t s) -> int {
     for (int gi = 0; gi < nrg; ++gi) {
       const auto& g = b->rgroups[gi];
-      if (g.chain != chain) continue;
+      if (g.chain != chain || g.set != set) continue;
       hipEvent_t end = batch_prof_begin(b, 3 * gi + (n == 0 ? 0 : (n == L ? 2 : 1)), s);
-      int e = tbs::launch_row_group(b->fp64, g.M, g.cb, g.nr, drow + (size_t)n * np + g.first,
+      int e = tbs::launch_row_group(b->fp64, g.M, g.cb, g.nr, drow + (size_t)n * nt + g.first,
                                     dst + g.starts_off, (int)g.members.size(), g.total, s);
       if (e) return bfail(b, TBS_ERR_HIP, std::string("grouped row pass: ") + hipGetErrorString((hipError_t)e));
       if (end && hipEventRecord(end, s) != hipSuccess) return bfail(b, TBS_ERR_HIP, "profile event");
     }
     return TBS_OK;
   };
-  auto cols = [&](int chain, hipStream_t s) -> int {
+  auto cols = [&](int chain, int set, hipStream_t s) -> int {
     for (int gi = 0; gi < (int)b->cgroups.size(); ++gi) {
       const auto& g = b->cgroups[gi];
-      if (g.chain != chain) continue;
+      if (g.chain != chain || g.set != set) continue;
       hipEvent_t end = batch_prof_begin(b, 3 * nrg + gi, s);
       int e = tbs::launch_col_group(b->fp64, g.M, g.nc, dcol + g.first, dst + g.starts_off,
                                     (int)g.members.size(), g.total, s);
@@ -836,14 +895,16 @@ int batch_enqueue(tbs_batch* b, int L) {
     return TBS_OK;
   };
   auto series = [&](int chain, hipStream_t s, hipEvent_t after_first) -> int {
-    for (int n = 0; n <= L; ++n) {
-      int rc = rows(chain, n, s);
-      if (rc) return rc;
-      if (n == 0 && after_first && hipEventRecord(after_first, s) != hipSuccess)
-        return bfail(b, TBS_ERR_HIP, "batch chain event");
-      if (n == L) break;
-      rc = cols(chain, s);
-      if (rc) return rc;
+    for (int set = 0; set < b->nsets; ++set) {
+      for (int n = 0; n <= L; ++n) {
+        int rc = rows(chain, set, n, s);
+        if (rc) return rc;
+        if (set == 0 && n == 0 && after_first && hipEventRecord(after_first, s) != hipSuccess)
+          return bfail(b, TBS_ERR_HIP, "batch chain event");
+        if (n == L) break;
+        rc = cols(chain, set, s);
+        if (rc) return rc;
+      }
     }
     return TBS_OK;
   };
@@ -1935,24 +1996,40 @@ int tbs_batch_solve(tbs_batch* b, const void* const* sources, const void* const*
           ensure_doubles(p, &p->resid, &p->resid_cap, (size_t)p->batch * L))
         return bfail(b, TBS_ERR_OOM, p->err);
     }
-    std::vector<tbs::RowArgs> rows((size_t)(L + 1) * np);
-    std::vector<tbs::ColArgs> cols((size_t)np);
-    for (int i = 0; i < np; ++i) {
+    const int nt = (int)b->tiles.size();
+    std::vector<tbs::RowArgs> rows((size_t)(L + 1) * nt);
+    std::vector<tbs::ColArgs> cols((size_t)nt);
+    for (int t = 0; t < nt; ++t) {
+      const tbs_batch::Tile& tl = b->tiles[t];
+      const int i = tl.plan;
       tbs_plan* p = b->plans[i];
-      const size_t per_term = (size_t)2 * p->batch * row_blocks(p);
+      const int nblk = row_blocks(p);
+      const size_t per_term = (size_t)2 * p->batch * nblk;
+      // the tile's right-hand sides: every per-RHS array moves by r0 slices
+      const size_t sp = (size_t)tl.r0 * p->P;                        // [rhs][P] values
+      const size_t xs = (size_t)tl.r0 * p->M[0] * p->N[1] * p->N[2];  // [rhs][kxb][rows][cb] values
+      const char* src = (const char*)sources[i] + sp * p->esz;
+      char* pout = (char*)p_outs[i] + sp * p->esz;
       for (int n = 0; n <= L; ++n) {
         tbs::RowArgs r;
         if (n == 0)
-          r = make_row_args(p, tbs::ROW_IN_SOURCE, tbs::ACC_NONE, 1, false, sources[i], nullptr,
+          r = make_row_args(p, tbs::ROW_IN_SOURCE, tbs::ACC_NONE, 1, false, src, nullptr,
                             nullptr, nullptr, nullptr, nullptr, nullptr);
         else
           r = make_row_args(p, tbs::ROW_IN_SPECTRAL, n == 1 ? tbs::ACC_INIT : tbs::ACC_ADD,
-                            n < L ? 1 : 0, false, nullptr, potentials[i], p_outs[i], nullptr,
-                            nullptr, nullptr, p->partials + (size_t)(n - 1) * per_term);
-        rows[(size_t)n * np + b->rpos[i]] = r;
+                            n < L ? 1 : 0, false, nullptr, potentials[i], pout, nullptr,
+                            nullptr, nullptr, p->partials + (size_t)(n - 1) * per_term + (size_t)2 * tl.r0 * nblk);
+        r.X = (char*)p->X + xs * p->esz;
+        if (r.c) r.c = (char*)r.c + sp * 4;
+        r.nrhs = tl.nrhs;
+        rows[(size_t)n * nt + b->rpos[t]] = r;
       }
       int nc = 0;
-      cols[b->cpos[i]] = make_conv2d_args(p, false, &nc);
+      tbs::ColArgs c = make_conv2d_args(p, false, &nc);
+      c.in = (const char*)p->X + xs * p->esz;
+      c.out = (char*)p->X + xs * p->esz;
+      c.nrhs = tl.nrhs;
+      cols[b->cpos[t]] = c;
     }
     const size_t rb = rows.size() * sizeof(tbs::RowArgs);
     if (b->d_row_bytes < rb) {
@@ -2217,7 +2294,7 @@ int tbs_batch_profile_enable(tbs_batch* b, int enable) {
 }
 
 int tbs_batch_profile_read(tbs_batch* b, int cap, int* nentries, int* kind, int* length, int* shape,
-                           int64_t* launches, double* ms, int* first, int* members) {
+                           int64_t* launches, double* ms, int* first, int* members, int* member_rhs) {
   if (!b || !nentries) return TBS_ERR_INVALID;
   const int nrg = (int)b->rgroups.size();
   const int ne = 3 * nrg + (int)b->cgroups.size();
@@ -2247,8 +2324,9 @@ int tbs_batch_profile_read(tbs_batch* b, int cap, int* nentries, int* kind, int*
     if (launches) launches[e] = b->prof_n[e];
     if (ms) ms[e] = b->prof_ms[e];
     if (first) first[e] = off;
-    for (int i : g.members) {
-      if (members) members[off] = i;
+    for (int t : g.members) {
+      if (members) members[off] = b->tiles[t].plan;
+      if (member_rhs) member_rhs[off] = b->tiles[t].nrhs;
       ++off;
     }
     b->prof_ms[e] = 0.0;

@@ -178,3 +178,33 @@ def test_batch_autotune_is_bitwise_neutral_and_cached(dev, tmp_path, monkeypatch
     assert all(" = " in ln and ln.split()[0] in ("batchrow", "batchcol") for ln in lines)
     for p in plans:
         p.close()
+
+
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+def test_tile_schedules_are_bitwise_one_set(dev, monkeypatch, dt):
+    """The cache-sized schedule (right-hand sides cut into tiles, tiles packed
+    into sets that run their whole series one after the other) against all
+    plans as one set of whole plans: the same arithmetic per right-hand side,
+    bitwise, with the residual histories; uneven tiles (5 RHS in tiles of
+    3 + 2 and 4 + 1) and many small sets included, with one grid of the full
+    broadband size."""
+    import paper_2507_13754_amd as tbs
+    cs = cases(nangles=3, nterms=5) + [workloads.broadband(40, nangles=5, nterms=5)]
+    plans, srcs, pots = build(dev, cs, dt)
+    monkeypatch.setenv("TBS_BATCH_CACHE_MB", "0")
+    whole = tbs.Batch(plans)
+    ref, rref = whole.solve(srcs, pots, 5, residual=True)
+    ref = [o.clone() for o in ref]
+    whole.close()
+    for cap, trhs in (("200", "4"), ("20", "3"), ("1", "1")):
+        monkeypatch.setenv("TBS_BATCH_CACHE_MB", cap)
+        monkeypatch.setenv("TBS_BATCH_TILE_RHS", trhs)
+        tiled = tbs.Batch(plans)
+        outs, res = tiled.solve(srcs, pots, 5, residual=True)
+        for a, b in zip(ref, outs):
+            assert torch.equal(a, b)
+        for a, b in zip(rref, res):
+            assert np.array_equal(a, b)
+        tiled.close()
+    for p in plans:
+        p.close()
