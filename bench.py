@@ -45,6 +45,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
+# FP32 vector peak of the code path: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x
+# 2.4 GHz.  The published 157.3 TFLOP/s counts packed (two-wide) FP32
+# instructions, which these kernels are compiled without.
+VALU_FP32_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 METRIC = "Born grid-point·terms/s + HBM GB/s frac, FP32 batched vs FP64 plain, 1 GPU"
 UNIT = "grid-point·terms/s"
 
@@ -218,7 +222,7 @@ def group_kernel_name(e) -> str:
     return f"{stem}<float, {e['length']}, ..., {e['shape']}, ...>"
 
 
-def run_broadband(dev, steps: int, warmup: int, fp64: bool, tune: bool):
+def run_broadband(dev, steps: int, warmup: int, fp64: bool, tune: bool, counters_only: bool = False):
     """The headline: 48 frequencies on their own grids, 16 steering angles
     each, 25 terms, one batch replayed as one recorded graph."""
     import torch
@@ -251,6 +255,11 @@ def run_broadband(dev, steps: int, warmup: int, fp64: bool, tune: bool):
         log(f"[bench] broadband {name}: 48 plans built (tabulated{', batch tuned' if tune else ''}) "
             f"in {t_build:.1f} s")
         outs = batch.solve(srcs, pots, L, outs=outs)
+        if counters_only:  # counter collection: two replays of the recorded graph, nothing else
+            batch.solve(srcs, pots, L, outs=outs)
+            torch.cuda.synchronize()
+            batch.close()
+            return None
         ms, wall = time_fn(lambda: batch.solve(srcs, pots, L, outs=outs), steps, warmup)
         log(f"[bench] broadband {name}: {ms:.2f} ms/step ({wall:.2f} wall)")
         fp = name == "c128"
@@ -289,7 +298,11 @@ def run_broadband(dev, steps: int, warmup: int, fp64: bool, tune: bool):
                       for i, r in tiles)
             per_term = e["launches"] / e["groups"] / nprof         # launches of one group per step
             t_term = e["ms"] / nprof / per_term                   # all groups of this kernel, one term
+            # column convolutions: radix-2 FLOP count at the smallest 5-smooth length
+            fl = (sum(col_conv_flops_2d(geo[i][0], geo[i][1], r, min_padded(geo[i][0])) for i, r in tiles)
+                  if kind == "col_conv" else 0.0)
             entries.append({"kind": kind, "length": length, "shape": shape, "grids": len(set(e["members"])),
+                            "alg_flops_per_term": fl,
                             "tiles": len(tiles), "rhs": sum(r for _, r in tiles),
                             "launches_per_step": e["launches"] / nprof, "grouped_launches_per_term": e["groups"],
                             "avg_launch_ms": e["ms"] / e["launches"], "ms_per_term": t_term,
@@ -307,16 +320,28 @@ def run_broadband(dev, steps: int, warmup: int, fp64: bool, tune: bool):
         del srcs, pots, outs
         torch.cuda.empty_cache()
     r32 = res["c64"]
+
+    def roofline(k):
+        """The kernel's roofline: HBM bytes for the row passes, FP32 VALU
+        FLOPs for the column convolutions (issue-bound: two transforms per
+        16 B of traffic per value; SQ counters in profiles/)."""
+        desc = (f"{group_kernel_name(k)}: {k['kind']}, FFT length {k['length']}, {k['grids']} grids "
+                f"({k['rhs']} RHS in {k['tiles']} tiles) in {k['grouped_launches_per_term']} grouped launches per term")
+        common = {"kernel": desc, "ms_per_term": k["ms_per_term"], "avg_launch_ms": k["avg_launch_ms"],
+                  "launches_per_step": k["launches_per_step"], "alg_bytes_per_term": k["alg_bytes_per_term"],
+                  "traffic": read_counters(group_kernel_re(k["kind"], k["length"], k["shape"]))}
+        if k["kind"] == "col_conv":
+            a = k["alg_flops_per_term"] / (k["ms_per_term"] * 1e-3) / 1e12
+            return {"bound": "alu", "achieved": a, "peak": VALU_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": a / VALU_FP32_PEAK_TFLOPS, "alg_flops_per_term": k["alg_flops_per_term"],
+                    "hbm_GBps": k["GBps"], **common}
+        return {"bound": "hbm", "achieved": k["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": k["GBps"] / HBM_PEAK_GBS, **common}
+
     dom = r32["kernels"][0]
-    traffic = read_counters(group_kernel_re(dom["kind"], dom["length"], dom["shape"]))
-    roof = {"bound": "hbm", "achieved": dom["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": dom["GBps"] / HBM_PEAK_GBS,
-            "traffic": traffic,
-            "kernel": (f"{group_kernel_name(dom)}: {dom['kind']}, FFT length {dom['length']}, "
-                       f"{dom['grids']} grids ({dom['rhs']} RHS in {dom['tiles']} tiles) in "
-                       f"{dom['grouped_launches_per_term']} grouped launches per term"),
-            "alg_bytes_per_term": dom["alg_bytes_per_term"], "ms_per_term": dom["ms_per_term"],
-            "avg_launch_ms": dom["avg_launch_ms"], "launches_per_step": dom["launches_per_step"]}
+    roof = roofline(dom)
+    row_dom = next(k for k in r32["kernels"] if k["kind"].startswith("row"))
+    r32["roofline_row_pass"] = roofline(row_dom)
     out = {"r32": r32, "roofline": roof, "L": L, "geo": geo}
     if "c128" in res:
         r64 = res["c128"]
@@ -746,11 +771,15 @@ def summarize_trace(src: str, out: str, command: str, title: str, skip_before: s
     log(f"[bench] wrote {out}")
 
 
-def summarize_counters(src: str, command: str):
-    """FETCH_SIZE / WRITE_SIZE per dispatch (KiB, median over dispatches) of
-    every grouped pass kernel from <src>/fetch and <src>/write, scaled by what
-    the same counters read for the 256 MiB calibration copy, into
-    profiles/counters_broadband.json (+ .md)."""
+def summarize_counters(src: str, command: str, nplans: int = 48, nterms: int = 25):
+    """FETCH_SIZE / WRITE_SIZE (KiB) of every grouped pass kernel from
+    <src>/fetch and <src>/write, scaled by what the same counters read for the
+    256 MiB calibration copy, per term: summed over all dispatches of the
+    kernel and divided by the solves of the run (one norm reduction per plan
+    and solve) times the passes per solve (nterms column passes, nterms + 1
+    row passes: first, middle and last averaged).  Into
+    profiles/counters_broadband.json (+ .md).  Run with the block shapes taken
+    from a TBS_TUNE_CACHE file, so that no tuning launches are counted."""
     vals = {}
     for kind, ctr in (("fetch", "FETCH_SIZE"), ("write", "WRITE_SIZE")):
         for r in _csv(os.path.join(src, kind, "run_counter_collection.csv")):
@@ -762,29 +791,32 @@ def summarize_counters(src: str, command: str):
         copies = [v for n, v in vals[kind] if "copyBuffer" in n]
         big = max(copies)
         factor[kind] = calib / statistics.median([v for v in copies if v > 0.4 * big])
+    solves = {k: sum(1 for n, _ in vals[k] if "k_finish_norms" in n) / nplans for k in vals}
     names = sorted({n for n, _ in vals["fetch"] if "_pass_group<" in n})
     kernels = {}
     md = ["# HBM traffic counters: broadband batch (48 grids x 16 RHS, 25 terms)", "",
           "Commands (repository root as working directory):", "", "    " + command, "",
-          "FETCH_SIZE and WRITE_SIZE in KiB per dispatch (median over the dispatches of each kernel; the",
-          "row-pass kernels run their first and last pass modes once per solve besides the middle ones),",
-          f"scaled by the 256 MiB calibration copy: read factor {factor['fetch']:.3f}, write factor "
-          f"{factor['write']:.3f}.", "",
-          "| kernel | dispatches | FETCH KiB | WRITE KiB | scaled bytes / launch |", "|---|---|---|---|---|"]
+          "FETCH_SIZE and WRITE_SIZE in KiB summed over every dispatch of each kernel (all sets of",
+          f"tiles), per term: divided by the {solves['fetch']:.0f} solves of the run times {nterms} column passes",
+          f"or {nterms + 1} row passes per solve (first, middle and last row passes averaged); scaled by the",
+          f"256 MiB calibration copy: read factor {factor['fetch']:.3f}, write factor {factor['write']:.3f}.", "",
+          "| kernel | dispatches | FETCH KiB / term | WRITE KiB / term | scaled bytes / term |", "|---|---|---|---|---|"]
     for n in names:
         f = [v for k, v in vals["fetch"] if k == n]
         w = [v for k, v in vals["write"] if k == n]
         if not f or not w:
             continue
-        fk, wk = statistics.median(f), statistics.median(w)
+        per = (nterms if "k_col_pass" in n else nterms + 1)
+        fk = sum(f) / (solves["fetch"] * per)
+        wk = sum(w) / (solves["write"] * per)
         traffic = 1024.0 * (fk * factor["fetch"] + wk * factor["write"])
-        kernels[n] = {"dispatches": len(f), "fetch_kib_median": fk, "write_kib_median": wk,
-                      "traffic_bytes_per_launch": traffic}
+        kernels[n] = {"dispatches": len(f), "fetch_kib_per_term": fk, "write_kib_per_term": wk,
+                      "traffic_bytes_per_term": traffic}
         md.append(f"| `{n}` | {len(f)} | {fk:.1f} | {wk:.1f} | {traffic:.4g} |")
     with open(os.path.join(ROOT, "profiles", "counters_broadband.json"), "w") as fh:
         json.dump({"workload": "broadband", "sources_sha256_16": kernel_sources_hash(),
-                   "read_factor": factor["fetch"], "write_factor": factor["write"], "kernels": kernels,
-                   "command": command}, fh, indent=1)
+                   "read_factor": factor["fetch"], "write_factor": factor["write"], "solves": solves,
+                   "kernels": kernels, "command": command}, fh, indent=1)
     md += ["", f"Kernel sources hash: {kernel_sources_hash()} (bench.py reports the traffic only while it matches)."]
     with open(os.path.join(ROOT, "profiles", "counters_broadband.md"), "w") as fh:
         fh.write("\n".join(md) + "\n")
@@ -802,6 +834,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the block-shape autotuner")
+    ap.add_argument("--counters-only", action="store_true",
+                    help="build the FP32 broadband batch, replay it twice and exit (for --pmc runs; "
+                         "with --calib-copy, the calibration copy after it)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
     ap.add_argument("--extra", default="absorb2d,harmonic3d,adjoint2d,density2d,paper",
@@ -832,7 +867,7 @@ def main():
     dev = torch.device("cuda:0")
     fp64 = not args.no_fp64
     tune = not args.no_tune
-    bb = run_broadband(dev, args.steps, args.warmup, fp64, tune)
+    bb = run_broadband(dev, args.steps, args.warmup, fp64 and not args.counters_only, tune, args.counters_only)
     if args.calib_copy:
         a = torch.empty(256 * 1024 * 1024 // 4, dtype=torch.float32, device=dev).fill_(1.0)
         b = torch.empty_like(a)
@@ -841,6 +876,8 @@ def main():
         torch.cuda.synchronize()
         del a, b
         log("[bench] calibration copy of 256 MiB done (3 launches)")
+    if args.counters_only:
+        return
     r32 = bb["r32"]
     L = bb["L"]
     B = bb["geo"][0][2]
@@ -861,12 +898,14 @@ def main():
         "config": {"workload": "broadband: 48 frequencies 2-8 MHz (f_i = 2 + 6 i/47 MHz), each on its own "
                                "lambda/6 grid over 4 x 4 cm (312^2 .. 1247^2), 16-blob absorbing-dispersive "
                                "medium, 64-element array with 16 steering angles (-30..30 deg) per frequency, "
-                               "25 terms, one batch replayed as one recorded HIP graph",
+                               "25 terms, one batch (right-hand sides in tiles of 4, cache-sized sets run one "
+                               "after another) replayed as one recorded HIP graph",
                    "grids": len(bb["geo"]), "rhs_per_grid": B, "nterms": L,
                    "physical_points": int(sum(g[0] * g[1] for g in bb["geo"])),
                    "padded_lengths": lengths,
                    "plan_dtype": "complex64 + Kahan-compensated sum (compensation stored as bf16)"},
         "roofline": bb["roofline"],
+        "roofline_row_pass": r32["roofline_row_pass"],
         "step_roofline": {"alg_bytes_per_step": r32["bytes"],
                           "achieved_GBps": r32["bytes"] / (r32["ms"] * 1e-3) / 1e9,
                           "frac": r32["bytes"] / (r32["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
