@@ -32,6 +32,33 @@ extern "C" int tbs_hostcheck_dft(int R, int inv, const double* in, double* out) 
 #undef C
 }
 
+namespace {
+template <int R, bool INV>
+void run_half(const double* in, double* out) {
+  tbs::cx<double> a[R];
+  for (int i = 0; i < R; ++i) a[i] = i < R / 2 ? tbs::cx<double>{in[2 * i], in[2 * i + 1]} : tbs::cx<double>{0.0, 0.0};
+  tbs::dft_half<R, INV>(a);
+  for (int i = 0; i < R; ++i) {
+    out[2 * i] = a[i].x;
+    out[2 * i + 1] = a[i].y;
+  }
+}
+}  // namespace
+
+// The first-stage DFTs of a zero-padded line: in holds the R/2 nonzero
+// inputs, out the R outputs.
+extern "C" int tbs_hostcheck_dft_half(int R, int inv, const double* in, double* out) {
+#define C(r)                                                      \
+  case r:                                                         \
+    if (inv) run_half<r, true>(in, out); else run_half<r, false>(in, out); \
+    return 0;
+  switch (R) {
+    C(2) C(4) C(8) C(16)
+    default: return -1;
+  }
+#undef C
+}
+
 extern "C" int tbs_hostcheck_stages(int M, int E, int* radices) {
   tbs::Stages s = tbs::make_stages(M, E);
   for (int i = 0; i < s.n; ++i) radices[i] = s.r[i];

@@ -236,6 +236,80 @@ __host__ __device__ __forceinline__ void dft(cx<T> (&a)[R]) {
   }
 }
 
+// ---- DFTs of R values whose upper half is zero ----------------------------
+// The first stage of a transform of a zero-padded line (the upper half of
+// the line is zero: registers j >= E/2, i.e. inputs r >= R/2 of every
+// first-stage butterfly).  Under IEEE rules x + 0 is not x (for x = -0), so
+// the compiler keeps those additions; these forms leave them out.  Outputs
+// equal the full DFT's up to the sign of zero results.
+
+// X_k = sum_{r < R/2} a_r w_R^{rk}, R = 4: X0,2 = a0 +- a1, X1,3 = a0 +- w4 a1.
+template <bool INV, typename T>
+__host__ __device__ __forceinline__ void dft4_half(cx<T>& a0, cx<T>& a1, cx<T>& a2, cx<T>& a3) {
+  const cx<T> b = rot4<INV>(a1);
+  a2 = a0 - a1;
+  a3 = a0 - b;
+  const cx<T> x0 = a0;
+  a0 = x0 + a1;
+  a1 = x0 + b;
+}
+
+template <int R, bool INV, typename T>
+__host__ __device__ __forceinline__ void dft_half(cx<T> (&a)[R]) {
+  if constexpr (R == 2) {
+    a[1] = a[0];
+  } else if constexpr (R == 4) {
+    dft4_half<INV>(a[0], a[1], a[2], a[3]);
+  } else if constexpr (R == 8) {
+    // radix-2 DIT split: the even and the odd halves each have their upper
+    // two inputs zero
+    cx<T> e0 = a[0], e1 = a[2], e2, e3;
+    cx<T> o0 = a[1], o1 = a[3], o2, o3;
+    dft4_half<INV>(e0, e1, e2, e3);
+    dft4_half<INV>(o0, o1, o2, o3);
+    o1 = rot16<INV, 2>(o1);
+    o2 = rot16<INV, 4>(o2);
+    o3 = rot16<INV, 6>(o3);
+    a[0] = e0 + o0; a[4] = e0 - o0;
+    a[1] = e1 + o1; a[5] = e1 - o1;
+    a[2] = e2 + o2; a[6] = e2 - o2;
+    a[3] = e3 + o3; a[7] = e3 - o3;
+  } else if constexpr (R == 16) {
+    // 4 x 4 as in dft16: the first-level DFTs take a[n2], a[4+n2] (a[8+n2],
+    // a[12+n2] are zero)
+    cx<T> b[16];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+      cx<T> x0 = a[n2], x1 = a[4 + n2], x2, x3;
+      dft4_half<INV>(x0, x1, x2, x3);
+      b[0 + n2] = x0;
+      b[4 + n2] = x1;
+      b[8 + n2] = x2;
+      b[12 + n2] = x3;
+    }
+    b[4 + 1] = rot16<INV, 1>(b[4 + 1]);
+    b[4 + 2] = rot16<INV, 2>(b[4 + 2]);
+    b[4 + 3] = rot16<INV, 3>(b[4 + 3]);
+    b[8 + 1] = rot16<INV, 2>(b[8 + 1]);
+    b[8 + 2] = rot16<INV, 4>(b[8 + 2]);
+    b[8 + 3] = rot16<INV, 6>(b[8 + 3]);
+    b[12 + 1] = rot16<INV, 3>(b[12 + 1]);
+    b[12 + 2] = rot16<INV, 6>(b[12 + 2]);
+    b[12 + 3] = rot16<INV, 9>(b[12 + 3]);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+      cx<T> x0 = b[4 * k1 + 0], x1 = b[4 * k1 + 1], x2 = b[4 * k1 + 2], x3 = b[4 * k1 + 3];
+      dft4<INV>(x0, x1, x2, x3);
+      a[k1 + 0] = x0;
+      a[k1 + 4] = x1;
+      a[k1 + 8] = x2;
+      a[k1 + 12] = x3;
+    }
+  } else {
+    static_assert(R % 2 == 0, "a zero upper half needs an even radix");
+  }
+}
+
 // ---- stage plan -----------------------------------------------------------
 
 struct Stages {
@@ -459,7 +533,7 @@ __host__ __device__ constexpr int xwrite_slot(Swz p, int TPT, int L, int R, int 
 // buffer of M (+pad) values, halving the LDS a line needs (four barriers per
 // exchange instead of two).  Otherwise complex values go through LDS at once.
 // TWC: the twiddle factors come from twc (tw_load), else from the table tw.
-template <typename T, int M, int E, bool INV, bool SPLIT, bool TWC, int S>
+template <typename T, int M, int E, bool INV, bool SPLIT, bool TWC, int S, bool ZIN>
 __device__ __forceinline__ void fft_stages(cx<T> (&v)[E], void* __restrict__ shv,
                                            const cx<T>* __restrict__ tw, const cx<T>* twc, int t) {
   constexpr Stages st = make_stages(M, E);
@@ -492,7 +566,10 @@ __device__ __forceinline__ void fft_stages(cx<T> (&v)[E], void* __restrict__ shv
         a[r] = INV ? cmulc(a[r], w) : cmul(a[r], w);
       }
     }
-    dft<R, INV>(a);
+    // a zero-padded line (ZIN): the first stage's inputs r >= R/2 are the
+    // zero upper half of the registers
+    if constexpr (ZIN && S == 0 && R % 2 == 0 && (R / 2) * NB == E / 2) dft_half<R, INV>(a);
+    else dft<R, INV>(a);
     if constexpr (LOCAL) {
 #pragma unroll
       for (int r = 0; r < R; ++r)
@@ -509,7 +586,7 @@ __device__ __forceinline__ void fft_stages(cx<T> (&v)[E], void* __restrict__ shv
   if constexpr (LOCAL) {
 #pragma unroll
     for (int j = 0; j < E; ++j) v[j] = w[j];
-    fft_stages<T, M, E, INV, SPLIT, TWC, S + 1>(v, shv, tw, twc, t);
+    fft_stages<T, M, E, INV, SPLIT, TWC, S + 1, ZIN>(v, shv, tw, twc, t);
   } else if constexpr (!LAST) {
     if constexpr (SPLIT) {
       T* sh = (T*)shv;
@@ -538,17 +615,18 @@ __device__ __forceinline__ void fft_stages(cx<T> (&v)[E], void* __restrict__ shv
       for (int j = 0; j < E; ++j) v[j] = sh[xread_slot(XL, TPT, t, j)];
       __syncthreads();
     }
-    fft_stages<T, M, E, INV, SPLIT, TWC, S + 1>(v, shv, tw, twc, t);
+    fft_stages<T, M, E, INV, SPLIT, TWC, S + 1, ZIN>(v, shv, tw, twc, t);
   }
 }
 
 // Full transform of the thread's E registers (strided layout in and out).
 // Every thread of the block must call it (it contains block barriers).
 // shv: this line's LDS buffer, lds_len(M, .) elements of T (SPLIT) or cx<T>.
-template <typename T, int M, int E, bool INV, bool SPLIT>
+// ZIN: the registers j >= E/2 (the upper half of the line) hold zeros.
+template <typename T, int M, int E, bool INV, bool SPLIT, bool ZIN = false>
 __device__ __forceinline__ void fft(cx<T> (&v)[E], void* __restrict__ shv,
                                     const cx<T>* __restrict__ tw, int t) {
-  fft_stages<T, M, E, INV, SPLIT, false, 0>(v, shv, tw, nullptr, t);
+  fft_stages<T, M, E, INV, SPLIT, false, 0, ZIN>(v, shv, tw, nullptr, t);
 }
 
 // Loads the factors of stages S.. of thread t into twc (tw_cache_size(M, E)
@@ -573,9 +651,9 @@ __device__ __forceinline__ void tw_load(cx<T>* twc, const cx<T>* __restrict__ tw
 }
 
 // The transform with the factors already in registers (tw_load).
-template <typename T, int M, int E, bool INV, bool SPLIT>
+template <typename T, int M, int E, bool INV, bool SPLIT, bool ZIN = false>
 __device__ __forceinline__ void fft_cached(cx<T> (&v)[E], void* __restrict__ shv, const cx<T>* twc, int t) {
-  fft_stages<T, M, E, INV, SPLIT, true, 0>(v, shv, nullptr, twc, t);
+  fft_stages<T, M, E, INV, SPLIT, true, 0, ZIN>(v, shv, nullptr, twc, t);
 }
 
 }  // namespace tbs

@@ -383,9 +383,9 @@ __device__ __forceinline__ void row_pass_body(const RowArgs& a, const int lb) {
     }
   }
 
-  if (a.out_spec) {
-    if constexpr (TWR) fft_cached<T, M, E, false, SPLIT>(v, shr, twc, t);
-    else fft<T, M, E, false, SPLIT>(v, shr, tw, t);
+  if (a.out_spec) {  // registers j >= E/2 hold zeros (the padding)
+    if constexpr (TWR) fft_cached<T, M, E, false, SPLIT, true>(v, shr, twc, t);
+    else fft<T, M, E, false, SPLIT, true>(v, shr, tw, t);
     if (valid) {
 #pragma unroll
       for (int j = 0; j < E; ++j) {
@@ -466,8 +466,8 @@ __device__ __forceinline__ void col_pass_body(const ColArgs& a, const int lb) {
     }
   }
   if constexpr (OP != COL_INV) {
-    if constexpr (TWR) fft_cached<T, M, E, false, SPLIT>(v, shc, twc, tt);
-    else fft<T, M, E, false, SPLIT>(v, shc, tw, tt);
+    if constexpr (TWR) fft_cached<T, M, E, false, SPLIT, HALF_IN>(v, shc, twc, tt);
+    else fft<T, M, E, false, SPLIT, HALF_IN>(v, shc, tw, tt);
   }
   if constexpr (CONV) {
 #pragma unroll

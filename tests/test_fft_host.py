@@ -32,6 +32,25 @@ def test_radix_butterfly(hc, R, inv):
         assert np.max(np.abs(y - ref)) < 1e-14 * np.max(np.abs(ref)) * R
 
 
+@pytest.mark.parametrize("R", [2, 4, 8, 16])
+@pytest.mark.parametrize("inv", [0, 1])
+def test_first_stage_of_zero_padded_line(hc, R, inv):
+    """The pruned first-stage butterflies (inputs R/2.. zero) equal the DFT of
+    the zero-padded input; a dropped term or a wrong rotation fails."""
+    rng = np.random.default_rng(100 + R + inv)
+    for _ in range(5):
+        x = rng.standard_normal(R // 2) + 1j * rng.standard_normal(R // 2)
+        inp = np.empty(R)
+        inp[0::2], inp[1::2] = x.real, x.imag
+        out = np.zeros(2 * R)
+        assert hc.tbs_hostcheck_dft_half(R, inv, inp.ctypes.data_as(ctypes.c_void_p),
+                                         out.ctypes.data_as(ctypes.c_void_p)) == 0
+        y = out[0::2] + 1j * out[1::2]
+        xp = np.concatenate([x, np.zeros(R // 2)])
+        ref = np.fft.ifft(xp) * R if inv else np.fft.fft(xp)
+        assert np.max(np.abs(y - ref)) < 1e-14 * max(1.0, np.max(np.abs(ref)))
+
+
 @pytest.mark.parametrize("M,E", [(16, 4), (32, 4), (64, 4), (128, 8), (256, 8), (512, 8),
                                  (1024, 16), (2048, 16), (4096, 16), (2500, 20), (1000, 40)])
 def test_stage_plan(hc, M, E):
