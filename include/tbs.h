@@ -373,13 +373,15 @@ int tbs_batch_solve(tbs_batch *batch, const void *const *sources, const void *co
 
 /* Choose the block shapes of the batch's grouped launches (rows per row-pass
  * block for all plans of one x length, columns per convolution block for all
- * plans of one y length) by timing each bitwise-neutral candidate as one
- * grouped launch on the given buffers (same meaning as in tbs_batch_solve;
- * the contents of p_outs are undefined afterwards), and regroup.  Choices are
- * kept per device model, dtype, length and member shapes for the life of the
- * process, and in the file named by the environment variable TBS_TUNE_CACHE
- * when it is set (read on first use, appended to; tbs_plan_autotune shares
- * it).  Synchronises the first plan's stream; drops the recorded graph. */
+ * plans of one y length) by timing each bitwise-neutral candidate as the
+ * grouped launches the solves make for it (one per set of tiles, a middle
+ * term) on the given buffers (same meaning as in tbs_batch_solve; the
+ * contents of p_outs are undefined afterwards), and regroup.  Choices are
+ * kept per device model, dtype, length, member shapes and tiling for the life
+ * of the process, and in the file named by the environment variable
+ * TBS_TUNE_CACHE when it is set (read on first use, appended to;
+ * tbs_plan_autotune shares it).  Synchronises the first plan's stream; drops
+ * the recorded graph. */
 int tbs_batch_autotune(tbs_batch *batch, const void *const *sources, const void *const *potentials,
                        void *const *p_outs);
 

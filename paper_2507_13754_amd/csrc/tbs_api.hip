@@ -667,6 +667,7 @@ struct tbs_batch {
   };
   std::vector<Tile> tiles;
   int nsets = 1;
+  int tile_rhs = 0, cache_mb = 0;  // the tiling the sets were made with (0: whole plans, one set)
   struct Group {
     int chain = 0, set = 0;
     int M = 0, cb = 4, nc = 0, nr = 0;
@@ -748,8 +749,11 @@ void batch_tile(tbs_batch* b) {
   if (!(cap > 0) || b->chains == 2) {
     for (int i = 0; i < nplans; ++i) b->tiles.push_back({i, 0, b->plans[i]->batch, 0});
     b->nsets = 1;
+    b->tile_rhs = b->cache_mb = 0;
     return;
   }
+  b->tile_rhs = trhs;
+  b->cache_mb = (int)(cap / 1e6 + 0.5);
   int set = 0;
   double acc = 0.0;
   bool empty = true;
@@ -840,6 +844,43 @@ int batch_group(tbs_batch* b) {
     return TBS_ERR_OOM;
   }
   return TBS_OK;
+}
+
+// Arguments of tile t's row pass of term n (0: the source in; L: the last)
+// and of its column convolution: the plan's arguments with every per-RHS
+// array moved to the tile's first right-hand side.
+tbs::RowArgs tile_row_args(tbs_batch* b, int t, int n, int L, const void* source, const void* V,
+                           void* p_out) {
+  const tbs_batch::Tile& tl = b->tiles[t];
+  tbs_plan* p = b->plans[tl.plan];
+  const int nblk = row_blocks(p);
+  const size_t per_term = (size_t)2 * p->batch * nblk;
+  const size_t sp = (size_t)tl.r0 * p->P;                        // [rhs][P] values
+  const size_t xs = (size_t)tl.r0 * p->M[0] * p->N[1] * p->N[2];  // [rhs][kxb][rows][cb] values
+  tbs::RowArgs r;
+  if (n == 0)
+    r = make_row_args(p, tbs::ROW_IN_SOURCE, tbs::ACC_NONE, 1, false, (const char*)source + sp * p->esz,
+                      nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+  else
+    r = make_row_args(p, tbs::ROW_IN_SPECTRAL, n == 1 ? tbs::ACC_INIT : tbs::ACC_ADD, n < L ? 1 : 0, false,
+                      nullptr, V, (char*)p_out + sp * p->esz, nullptr, nullptr, nullptr,
+                      p->partials + (size_t)(n - 1) * per_term + (size_t)2 * tl.r0 * nblk);
+  r.X = (char*)p->X + xs * p->esz;
+  if (r.c) r.c = (char*)r.c + sp * 4;
+  r.nrhs = tl.nrhs;
+  return r;
+}
+
+tbs::ColArgs tile_col_args(tbs_batch* b, int t) {
+  const tbs_batch::Tile& tl = b->tiles[t];
+  tbs_plan* p = b->plans[tl.plan];
+  const size_t xs = (size_t)tl.r0 * p->M[0] * p->N[1] * p->N[2];
+  int nc = 0;
+  tbs::ColArgs c = make_conv2d_args(p, false, &nc);
+  c.in = (const char*)p->X + xs * p->esz;
+  c.out = (char*)p->X + xs * p->esz;
+  c.nrhs = tl.nrhs;
+  return c;
 }
 
 // Start event of a profiled launch (entry e); returns the end event to record
@@ -2000,36 +2041,10 @@ int tbs_batch_solve(tbs_batch* b, const void* const* sources, const void* const*
     std::vector<tbs::RowArgs> rows((size_t)(L + 1) * nt);
     std::vector<tbs::ColArgs> cols((size_t)nt);
     for (int t = 0; t < nt; ++t) {
-      const tbs_batch::Tile& tl = b->tiles[t];
-      const int i = tl.plan;
-      tbs_plan* p = b->plans[i];
-      const int nblk = row_blocks(p);
-      const size_t per_term = (size_t)2 * p->batch * nblk;
-      // the tile's right-hand sides: every per-RHS array moves by r0 slices
-      const size_t sp = (size_t)tl.r0 * p->P;                        // [rhs][P] values
-      const size_t xs = (size_t)tl.r0 * p->M[0] * p->N[1] * p->N[2];  // [rhs][kxb][rows][cb] values
-      const char* src = (const char*)sources[i] + sp * p->esz;
-      char* pout = (char*)p_outs[i] + sp * p->esz;
-      for (int n = 0; n <= L; ++n) {
-        tbs::RowArgs r;
-        if (n == 0)
-          r = make_row_args(p, tbs::ROW_IN_SOURCE, tbs::ACC_NONE, 1, false, src, nullptr,
-                            nullptr, nullptr, nullptr, nullptr, nullptr);
-        else
-          r = make_row_args(p, tbs::ROW_IN_SPECTRAL, n == 1 ? tbs::ACC_INIT : tbs::ACC_ADD,
-                            n < L ? 1 : 0, false, nullptr, potentials[i], pout, nullptr,
-                            nullptr, nullptr, p->partials + (size_t)(n - 1) * per_term + (size_t)2 * tl.r0 * nblk);
-        r.X = (char*)p->X + xs * p->esz;
-        if (r.c) r.c = (char*)r.c + sp * 4;
-        r.nrhs = tl.nrhs;
-        rows[(size_t)n * nt + b->rpos[t]] = r;
-      }
-      int nc = 0;
-      tbs::ColArgs c = make_conv2d_args(p, false, &nc);
-      c.in = (const char*)p->X + xs * p->esz;
-      c.out = (char*)p->X + xs * p->esz;
-      c.nrhs = tl.nrhs;
-      cols[b->cpos[t]] = c;
+      const int i = b->tiles[t].plan;
+      for (int n = 0; n <= L; ++n)
+        rows[(size_t)n * nt + b->rpos[t]] = tile_row_args(b, t, n, L, sources[i], potentials[i], p_outs[i]);
+      cols[b->cpos[t]] = tile_col_args(b, t);
     }
     const size_t rb = rows.size() * sizeof(tbs::RowArgs);
     if (b->d_row_bytes < rb) {
@@ -2125,22 +2140,30 @@ int tbs_batch_autotune(tbs_batch* b, const void* const* sources, const void* con
   batch_drop_graph(b);
   const hipStream_t s = b->plans[0]->stream;
   for (tbs_plan* p : b->plans) {
-    // norm partials of one row pass for any block shape (at most one row per block)
-    if (ensure_doubles(p, &p->partials, &p->partials_cap, (size_t)2 * p->batch * p->N[1]))
+    // norm partials of two row passes (a middle term) for any block shape
+    // (at most one row per block)
+    if (ensure_doubles(p, &p->partials, &p->partials_cap, (size_t)4 * p->batch * p->N[1]))
       return bfail(b, TBS_ERR_OOM, p->err);
   }
+  // the tiles and sets the solves will run (the block shapes do not change them)
+  int grc0 = batch_group(b);
+  if (grc0) return bfail(b, grc0, "batch tables");
+  const int nt = (int)b->tiles.size();
   const std::string tag = device_tag(b->plans[0]->device) + (b->fp64 ? " c128" : " c64");
+  const std::string sched = b->nsets > 1 || b->tile_rhs
+                                ? " tiles" + std::to_string(b->tile_rhs) + " cache" + std::to_string(b->cache_mb)
+                                : std::string();
   hipEvent_t e0 = nullptr, e1 = nullptr;
   void* d_desc = nullptr;
   void* d_st = nullptr;
-  const size_t desc_bytes = (size_t)np * std::max(sizeof(tbs::RowArgs), sizeof(tbs::ColArgs));
+  const size_t desc_bytes = (size_t)nt * std::max(sizeof(tbs::RowArgs), sizeof(tbs::ColArgs));
   int rc = TBS_OK;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess ||
-      hipMalloc(&d_desc, desc_bytes) != hipSuccess || hipMalloc(&d_st, (size_t)np * sizeof(int)) != hipSuccess) {
+      hipMalloc(&d_desc, desc_bytes) != hipSuccess || hipMalloc(&d_st, (size_t)nt * sizeof(int)) != hipSuccess) {
     (void)hipGetLastError();
     rc = bfail(b, TBS_ERR_OOM, "batch tuning buffers");
   }
-  // time one grouped launch over all plans of one length (2 warm-up, 3 timed)
+  // time one grouped launch (2 warm-up, 3 timed)
   auto timeit = [&](auto&& launch) -> double {
     for (int w = 0; w < 2; ++w) launch();
     (void)hipEventRecord(e0, s);
@@ -2151,7 +2174,6 @@ int tbs_batch_autotune(tbs_batch* b, const void* const* sources, const void* con
     (void)hipEventElapsedTime(&ms, e0, e1);
     return ms / 3.0;
   };
-  // rows: one choice of rows per block for all plans of one x length
   std::map<int, std::vector<int>> by_row;
   std::map<std::pair<int, int>, std::vector<int>> by_col;
   for (int i = 0; i < np; ++i) {
@@ -2168,48 +2190,73 @@ int tbs_batch_autotune(tbs_batch* b, const void* const* sources, const void* con
     for (const auto& q : parts) k += (k.empty() ? "" : ",") + q;
     return k;
   };
+  // the tiles of each set whose plan is one of mem: the launches the solves
+  // make for one pass kind of one length, set by set
+  auto set_tiles = [&](const std::vector<int>& mem) {
+    std::vector<std::vector<int>> out((size_t)b->nsets);
+    for (int t = 0; t < nt; ++t)
+      if (std::find(mem.begin(), mem.end(), b->tiles[t].plan) != mem.end())
+        out[(size_t)b->tiles[t].set].push_back(t);
+    return out;
+  };
+  // one candidate: every set's grouped launch of these tiles, timed and summed
+  auto time_sets = [&](const std::vector<std::vector<int>>& sets, bool row, int M, int cb, int shape) -> double {
+    double total_ms = 0.0;
+    for (const auto& ts : sets) {
+      if (ts.empty() || rc) continue;
+      std::vector<int> st;
+      int total = 0;
+      std::vector<tbs::RowArgs> dr;
+      std::vector<tbs::ColArgs> dc;
+      for (int t : ts) {
+        const int i = b->tiles[t].plan;
+        st.push_back(total);
+        if (row) {
+          dr.push_back(tile_row_args(b, t, 2, 3, sources[i], potentials[i], p_outs[i]));
+          total += row_blocks(b->plans[i]) * b->tiles[t].nrhs;
+        } else {
+          dc.push_back(tile_col_args(b, t));
+          total += dc.back().nrhs * dc.back().n1 * dc.back().n0;
+        }
+      }
+      const size_t db = row ? dr.size() * sizeof(tbs::RowArgs) : dc.size() * sizeof(tbs::ColArgs);
+      if (hipMemcpy(d_desc, row ? (const void*)dr.data() : (const void*)dc.data(), db, hipMemcpyHostToDevice) !=
+              hipSuccess ||
+          hipMemcpy(d_st, st.data(), st.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipGetLastError();
+        rc = bfail(b, TBS_ERR_HIP, "batch tuning tables");
+        break;
+      }
+      int le = 0;
+      total_ms += timeit([&] {
+        const int e = row ? tbs::launch_row_group(b->fp64, M, cb, shape, (const tbs::RowArgs*)d_desc,
+                                                  (const int*)d_st, (int)ts.size(), total, s)
+                          : tbs::launch_col_group(b->fp64, M, shape, (const tbs::ColArgs*)d_desc,
+                                                  (const int*)d_st, (int)ts.size(), total, s);
+        if (e) le = e;
+      });
+      if (le) rc = bfail(b, TBS_ERR_HIP, std::string("batch tuning launch: ") + hipGetErrorString((hipError_t)le));
+    }
+    return total_ms;
+  };
+  // rows: one choice of rows per block for all plans of one x length
   for (auto it = by_row.begin(); !rc && it != by_row.end(); ++it) {
     const int M = it->first;
     const std::vector<int>& mem = it->second;
     int cand[8];
     const int n = tbs::row_nr_candidates(M, b->fp64, cand);
-    const std::string key = "batchrow " + tag + " M" + std::to_string(M) + " " + members_key(mem);
+    const std::string key = "batchrow " + tag + " M" + std::to_string(M) + " " + members_key(mem) + sched;
     std::vector<int> v;
     int pick = cand[0];
     if (tune_lookup(key, &v) && v.size() == 1 && in_list(v[0], cand, n)) {
       pick = v[0];
     } else if (n > 1) {
+      const auto sets = set_tiles(mem);
       double best = 1e30;
       for (int ci = 0; ci < n && !rc; ++ci) {
-        std::vector<tbs::RowArgs> d;
-        std::vector<int> st;
-        int total = 0;
-        for (int i : mem) {
-          tbs_plan* p = b->plans[i];
-          p->row_nr = cand[ci];
-          d.push_back(make_row_args(p, tbs::ROW_IN_SPECTRAL, tbs::ACC_ADD, 1, false, nullptr, potentials[i],
-                                    p_outs[i], nullptr, nullptr, nullptr, p->partials));
-          st.push_back(total);
-          total += row_blocks(p) * p->batch;
-        }
-        if (hipMemcpy(d_desc, d.data(), d.size() * sizeof(tbs::RowArgs), hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemcpy(d_st, st.data(), st.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
-          (void)hipGetLastError();
-          rc = bfail(b, TBS_ERR_HIP, "batch tuning tables");
-          break;
-        }
-        int le = 0;
-        const double t = timeit([&] {
-          const int e = tbs::launch_row_group(b->fp64, M, b->plans[mem[0]]->cb, cand[ci],
-                                              (const tbs::RowArgs*)d_desc, (const int*)d_st, (int)mem.size(),
-                                              total, s);
-          if (e) le = e;
-        });
-        if (le) {
-          rc = bfail(b, TBS_ERR_HIP, std::string("batch tuning launch: ") + hipGetErrorString((hipError_t)le));
-          break;
-        }
-        if (t < best) {
+        for (int i : mem) b->plans[i]->row_nr = cand[ci];
+        const double t = time_sets(sets, true, M, b->plans[mem[0]]->cb, cand[ci]);
+        if (!rc && t < best) {
           best = t;
           pick = cand[ci];
         }
@@ -2226,42 +2273,18 @@ int tbs_batch_autotune(tbs_batch* b, const void* const* sources, const void* con
     int cand[8];
     const int n = tbs::conv_nc_candidates(M, b->fp64, cb, cand);
     const std::string key = "batchcol " + tag + " M" + std::to_string(M) + " cb" + std::to_string(cb) + " " +
-                            members_key(mem);
+                            members_key(mem) + sched;
     std::vector<int> v;
     int pick = cand[0];
     if (tune_lookup(key, &v) && v.size() == 1 && in_list(v[0], cand, n)) {
       pick = v[0];
     } else if (n > 1) {
+      const auto sets = set_tiles(mem);
       double best = 1e30;
       for (int ci = 0; ci < n && !rc; ++ci) {
-        std::vector<tbs::ColArgs> d;
-        std::vector<int> st;
-        int total = 0;
-        for (int i : mem) {
-          tbs_plan* p = b->plans[i];
-          p->conv_nc = cand[ci];
-          int nc = 0;
-          d.push_back(make_conv2d_args(p, false, &nc));
-          st.push_back(total);
-          total += d.back().nrhs * d.back().n1 * d.back().n0;
-        }
-        if (hipMemcpy(d_desc, d.data(), d.size() * sizeof(tbs::ColArgs), hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemcpy(d_st, st.data(), st.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
-          (void)hipGetLastError();
-          rc = bfail(b, TBS_ERR_HIP, "batch tuning tables");
-          break;
-        }
-        int le = 0;
-        const double t = timeit([&] {
-          const int e = tbs::launch_col_group(b->fp64, M, cand[ci], (const tbs::ColArgs*)d_desc,
-                                              (const int*)d_st, (int)mem.size(), total, s);
-          if (e) le = e;
-        });
-        if (le) {
-          rc = bfail(b, TBS_ERR_HIP, std::string("batch tuning launch: ") + hipGetErrorString((hipError_t)le));
-          break;
-        }
-        if (t < best) {
+        for (int i : mem) b->plans[i]->conv_nc = cand[ci];
+        const double t = time_sets(sets, false, M, cb, cand[ci]);
+        if (!rc && t < best) {
           best = t;
           pick = cand[ci];
         }
