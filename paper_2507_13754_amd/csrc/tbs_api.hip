@@ -650,10 +650,10 @@ struct tbs_batch {
   hipStream_t stream = nullptr;   // the batch's own stream (graphs are recorded and run here)
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   bool fp64 = false;
-  // Two chains: the plans split in two halves of equal work whose pass
-  // sequences run on two streams, the second one pass behind the first, so
-  // that one chain's memory-bound row pass can share the CUs with the other's
-  // ALU-bound column pass.
+  // Two chains: two pass sequences on two streams, the second one pass behind
+  // the first, so that one chain's launches fill the CUs the other's leave
+  // idle: with one set of whole plans, the plans split in two halves of equal
+  // work; with sets of tiles, the even and the odd sets.
   int chains = 1;
   hipStream_t stream2 = nullptr;
   hipEvent_t ev_lag = nullptr, ev_join = nullptr;
@@ -663,7 +663,7 @@ struct tbs_batch {
   // terms of one set, then the next), so that each set's data stays in the
   // 256 MB Infinity Cache between passes instead of streaming through HBM.
   struct Tile {
-    int plan = 0, r0 = 0, nrhs = 0, set = 0;
+    int plan = 0, r0 = 0, nrhs = 0, set = 0, chain = 0;
   };
   std::vector<Tile> tiles;
   int nsets = 1;
@@ -738,7 +738,8 @@ double tile_bytes(const tbs_plan* p, int nrhs) {
 // Split the plans into tiles of at most TBS_BATCH_TILE_RHS right-hand sides
 // (default 4) and pack consecutive tiles into sets of at most
 // TBS_BATCH_CACHE_MB megabytes of working set (default 256; 0: one set of
-// whole plans).  Two launch chains only run with a single set.
+// whole plans).  With two launch chains, even sets run on the first and odd
+// sets on the second.
 void batch_tile(tbs_batch* b) {
   const int nplans = (int)b->plans.size();
   double cap = 256e6;
@@ -746,8 +747,8 @@ void batch_tile(tbs_batch* b) {
   if (const char* e = std::getenv("TBS_BATCH_CACHE_MB")) cap = std::atof(e) * 1e6;
   if (const char* e = std::getenv("TBS_BATCH_TILE_RHS")) trhs = std::max(1, std::atoi(e));
   b->tiles.clear();
-  if (!(cap > 0) || b->chains == 2) {
-    for (int i = 0; i < nplans; ++i) b->tiles.push_back({i, 0, b->plans[i]->batch, 0});
+  if (!(cap > 0)) {
+    for (int i = 0; i < nplans; ++i) b->tiles.push_back({i, 0, b->plans[i]->batch, 0, b->chain_of[i]});
     b->nsets = 1;
     b->tile_rhs = b->cache_mb = 0;
     return;
@@ -766,7 +767,7 @@ void batch_tile(tbs_batch* b) {
         ++set;
         acc = 0.0;
       }
-      b->tiles.push_back({i, r0, nr, set});
+      b->tiles.push_back({i, r0, nr, set, b->chains == 2 ? set % 2 : 0});
       acc += w;
       empty = false;
     }
@@ -801,7 +802,7 @@ int batch_group(tbs_batch* b) {
   for (int t = 0; t < nt; ++t) {
     const tbs_batch::Tile& tl = b->tiles[t];
     tbs_plan* p = b->plans[tl.plan];
-    const int chain = b->chain_of[tl.plan];
+    const int chain = tl.chain;
     const int nr = p->row_nr ? p->row_nr : tbs::row_rows_per_block((int)p->M[0], p->fp64);
     find_or_add(b->rgroups, tl.set, chain, (int)p->M[0], p->cb, 0, nr).members.push_back(t);
     int nc = 0;
@@ -961,15 +962,15 @@ int batch_enqueue(tbs_batch* b, int L) {
     rc = series(1, b->stream, nullptr);
   }
   if (rc) return rc;
-  for (size_t i = 0; i < b->plans.size(); ++i) {
-    tbs_plan* p = b->plans[i];
-    int e = tbs::launch_finish_norms(p->partials, L, L, p->batch, row_blocks(p), p->resid,
-                                     two && b->chain_of[i] == 1 ? b->stream2 : b->stream);
-    if (e) return bfail(b, TBS_ERR_HIP, std::string("norms: ") + hipGetErrorString((hipError_t)e));
-  }
+  // a plan's tiles may sit on both chains: the norms after the join
   if (two && (hipEventRecord(b->ev_join, b->stream2) != hipSuccess ||
               hipStreamWaitEvent(b->stream, b->ev_join, 0) != hipSuccess))
     return bfail(b, TBS_ERR_HIP, "batch chain join");
+  for (size_t i = 0; i < b->plans.size(); ++i) {
+    tbs_plan* p = b->plans[i];
+    int e = tbs::launch_finish_norms(p->partials, L, L, p->batch, row_blocks(p), p->resid, b->stream);
+    if (e) return bfail(b, TBS_ERR_HIP, std::string("norms: ") + hipGetErrorString((hipError_t)e));
+  }
   return TBS_OK;
 }
 
