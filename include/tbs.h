@@ -359,8 +359,10 @@ typedef struct tbs_batch tbs_batch;
  * padded lengths coincide run in one grouped kernel launch per term.  With
  * the environment variable TBS_BATCH_CHAINS=2 (and two or more plans) the
  * whole plans are split in two halves of equal size whose pass sequences run
- * on two streams, one pass apart (one set).  Results are bitwise the same for
- * every schedule. */
+ * on two streams, one pass apart (one set).  TBS_BATCH_SHAPE="nr,nc" sets
+ * the rows and columns per block of the member plans whose shapes no tuner has
+ * chosen, where their lengths have those shapes.  Results are bitwise the
+ * same for every schedule and block shape. */
 int tbs_batch_create(tbs_batch **out, tbs_plan *const *plans, int nplans);
 
 /* The L-term series of every plan in the batch (the tbs_solve contract per

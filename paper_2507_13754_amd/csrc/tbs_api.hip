@@ -781,6 +781,21 @@ void batch_tile(tbs_batch* b) {
 // change.
 int batch_group(tbs_batch* b) {
   batch_tile(b);
+  // TBS_BATCH_SHAPE="nr,nc": rows and columns per block for the plans the
+  // tuners have not set, where the length has that shape (a check that every
+  // block shape gives the same results)
+  if (const char* e = std::getenv("TBS_BATCH_SHAPE")) {
+    int fnr = 0, fnc = 0;
+    if (std::sscanf(e, "%d,%d", &fnr, &fnc) == 2) {
+      for (tbs_plan* p : b->plans) {
+        int cand[8];
+        if (!p->row_nr && in_list(fnr, cand, tbs::row_nr_candidates((int)p->M[0], p->fp64, cand)))
+          p->row_nr = fnr;
+        if (!p->conv_nc && in_list(fnc, cand, tbs::conv_nc_candidates((int)p->M[1], p->fp64, p->cb, cand)))
+          p->conv_nc = fnc;
+      }
+    }
+  }
   const int nt = (int)b->tiles.size();
   b->rgroups.clear();
   b->cgroups.clear();

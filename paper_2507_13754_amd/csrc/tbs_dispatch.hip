@@ -39,7 +39,7 @@ int row_rows_per_block(int M, bool fp64) { return rows_per_block(M, fp64); }
 int spectral_block(int My, bool fp64) { return (fp64 && My >= 4096) ? 2 : 4; }
 
 int conv_cols_per_block(int M, bool fp64, int cb) {
-  const int want = M >= 2048 ? (fp64 ? TBS_NC_F64 : TBS_NC_F32) : (cb < 4 ? cb : 4);
+  const int want = conv_default_cols(M, fp64);
   return want < cb ? want : cb;
 }
 

@@ -174,6 +174,20 @@ constexpr int lds_only_waves(int M, int E, int lines, bool split) {
 // with the uniform loads of col_pass_body (2 and 6 registers; still the faster
 // variant).  The forward-only column pass (3D y) keeps loading from the
 // table: it runs one transform, and the lower occupancy made it 5 % slower.
+// The choice is made per length and pass, at the pass's default block shape
+// (rows_per_block; conv_default_cols), and holds for every block shape of
+// that length: where the factors come from changes how the compiler fuses the
+// products of the odd-radix butterflies (results then differ in the last
+// bits), so one choice per length keeps the block-shape candidates of the
+// autotuners bitwise-neutral.  FP32 column passes of 3 * 2^a lines keep the
+// factors in registers beyond the estimate (126 VGPRs at two lines per block,
+// 4 waves per SIMD, no spills; the 1536 column convolution of the broadband
+// batch 22.3 -> 18.0 ms per step; their row passes ran 34 % slower with
+// them), those of 5 * 2^a lines load them from the table (the tuned 1280 and
+// 2560 convolutions of that batch, 2 and 1 lines per block, ran 6 % and 1 %
+// slower with them in registers).
+constexpr int rows_per_block(int M, bool fp64);
+constexpr int conv_default_cols(int M, bool fp64);
 template <typename T>
 constexpr int tw_resident_vgprs(int M, int E, bool row) {
   const bool odd = (M & (M - 1)) != 0;
@@ -187,7 +201,11 @@ constexpr int tw_resident_vgprs(int M, int E, bool row) {
   return (int)(sizeof(T) / 2) * (E + tw_cache_size(M, E)) + rest * (int)(sizeof(T) / 4) + pre;
 }
 template <typename T>
-constexpr bool tw_resident(int M, int E, int lines, bool split, bool row) {
+constexpr bool tw_resident(int M, int E, bool split, bool row) {
+  constexpr bool F64 = sizeof(T) == 8;
+  if (!F64 && !row && M % 3 == 0) return TBS_TW_RESIDENT && M >= TBS_TW_MIN_M;
+  if (!F64 && !row && M % 5 == 0) return false;
+  const int lines = row ? rows_per_block(M, F64) : conv_default_cols(M, F64);
   const int budget = 512 / lds_only_waves<T>(M, E, lines, split);
   const int block_waves_simd = (lines * (M / E) + 255) / 256;  // a block's waves share 4 SIMDs
   const int floor_regs = 128 * (int)(sizeof(T) / 4) < 512 / block_waves_simd
@@ -209,7 +227,7 @@ constexpr int lds_waves_per_eu(int M, int E, int lines, bool split) {
   if (!TBS_OCC_HINT) return 1;
   int w = lds_only_waves<T>(M, E, lines, split);
   const int need = (sizeof(T) == 8 ? 10 : 5) * E + 40;
-  const int regs = (KIND != 0 && tw_resident<T>(M, E, lines, split, KIND == 1))
+  const int regs = (KIND != 0 && tw_resident<T>(M, E, split, KIND == 1))
                        ? tw_resident_vgprs<T>(M, E, KIND == 1)
                        : (need < 112 ? 112 : need);
   const int wr = 512 / regs;
@@ -257,7 +275,7 @@ __device__ __forceinline__ void row_pass_body(const RowArgs& a, const int lb) {
   const int64_t kbstride = (int64_t)a.nrows * CB;
 
   cx<T> v[E];
-  constexpr bool TWR = tw_resident<T>(M, E, NR, SPLIT, true);
+  constexpr bool TWR = tw_resident<T>(M, E, SPLIT, true);
   cx<T> twc[TWR ? tw_cache_size(M, E) : 1];
   if constexpr (TWR) tw_load<T, M, E>(twc, tw, t);
   double su = 0.0, sp = 0.0;
@@ -432,7 +450,7 @@ __device__ __forceinline__ void col_pass_body(const ColArgs& a, const int lb) {
   const int64_t ob = rhs * a.out_rs + blk * a.out_s1 + i0 * a.out_s0 + c0 + col;
 
   cx<T> v[E];
-  constexpr bool TWR = OP != COL_CONV_FULL && OP != COL_FWD && tw_resident<T>(M, E, NC, SPLIT, false);
+  constexpr bool TWR = OP != COL_CONV_FULL && OP != COL_FWD && tw_resident<T>(M, E, SPLIT, false);
   cx<T> twc[TWR ? tw_cache_size(M, E) : 1];
   constexpr int NLD = HALF_IN ? E / 2 : E;  // registers that can hold input
   // FP32 lines of 2048+: when every position of those registers is inside
@@ -588,6 +606,9 @@ constexpr int rows_per_block(int M, bool fp64) {
   return fp64 ? (M >= 4096 ? TBS_NR_F64 : (M >= 2048 && !split_lds(M, true) ? 2 : 4))
               : (M >= 2048 ? TBS_NR_F32 : 4);
 }
+// Columns per convolution block with a layout block of 4 columns (the
+// default of conv_cols_per_block).
+constexpr int conv_default_cols(int M, bool fp64) { return M >= 2048 ? (fp64 ? TBS_NC_F64 : TBS_NC_F32) : 4; }
 constexpr bool col_fits(int M, int NC, int esz) {
   const int le = split_lds(M, esz == 16) ? esz / 2 : esz;
   return (long)NC * lds_len(M, NC, le) * le <= 160L * 1024;

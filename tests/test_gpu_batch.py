@@ -156,15 +156,18 @@ def test_two_launch_chains_are_bitwise_one(dev, monkeypatch):
         p.close()
 
 
-def test_batch_autotune_is_bitwise_neutral_and_cached(dev, tmp_path, monkeypatch):
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+def test_batch_autotune_is_bitwise_neutral_and_cached(dev, tmp_path, monkeypatch, dt):
     """tbs_batch_autotune times the grouped launches' block shapes and
-    regroups: the fields after tuning equal the untuned ones bitwise, and the
-    choices land in the TBS_TUNE_CACHE file."""
+    regroups: the fields after tuning equal the untuned ones bitwise (every
+    block shape of a length keeps its twiddle factors where the default shape
+    does, 2560 lines with 1, 2 or 4 columns and 2 or 4 rows per block
+    included), and the choices land in the TBS_TUNE_CACHE file."""
     import paper_2507_13754_amd as tbs
     cache = tmp_path / "tune.txt"
     monkeypatch.setenv("TBS_TUNE_CACHE", str(cache))
-    cs = cases(nangles=2, nterms=5)
-    plans, srcs, pots = build(dev, cs, "c64")
+    cs = cases(nangles=2, nterms=5) + [workloads.broadband(40, nangles=2, nterms=5)]
+    plans, srcs, pots = build(dev, cs, dt)
     batch = tbs.Batch(plans)
     ref = [o.clone() for o in batch.solve(srcs, pots, 5)]
     outs = [torch.empty_like(o) for o in ref]
@@ -206,5 +209,36 @@ def test_tile_schedules_are_bitwise_one_set(dev, monkeypatch, dt):
         for a, b in zip(rref, res):
             assert np.array_equal(a, b)
         tiled.close()
+    for p in plans:
+        p.close()
+
+
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+def test_every_block_shape_is_bitwise_one(dev, monkeypatch, dt):
+    """Every block shape the tuners choose from (TBS_BATCH_SHAPE: 2 or 4 rows
+    and 1, 2 or 4 columns per block) gives the default shape's fields and
+    residual histories bitwise: a length keeps its twiddle factors where its
+    default shape does, whatever the shape (lines of 512, 640 and 768, and a
+    full-size grid with 2560 lines)."""
+    import paper_2507_13754_amd as tbs
+    cs = cases(nangles=2, nterms=5) + [workloads.broadband(40, nangles=2, nterms=5)]
+    plans, srcs, pots = build(dev, cs, dt)
+    base = tbs.Batch(plans)
+    ref, rref = base.solve(srcs, pots, 5, residual=True)
+    ref = [o.clone() for o in ref]
+    base.close()
+    for shape in ("2,1", "4,2", "2,4", "4,1"):
+        fresh, fsrcs, fpots = build(dev, cs, dt)
+        monkeypatch.setenv("TBS_BATCH_SHAPE", shape)
+        b = tbs.Batch(fresh)
+        outs, res = b.solve(fsrcs, fpots, 5, residual=True)
+        for a, g in zip(ref, outs):
+            assert torch.equal(a, g), shape
+        for a, g in zip(rref, res):
+            assert np.array_equal(a, g), shape
+        b.close()
+        monkeypatch.delenv("TBS_BATCH_SHAPE")
+        for p in fresh:
+            p.close()
     for p in plans:
         p.close()
