@@ -185,7 +185,7 @@ constexpr int lds_only_waves(int M, int E, int lines, bool split) {
 // batch 22.3 -> 18.0 ms per step; their row passes ran 34 % slower with
 // them), those of 5 * 2^a lines load them from the table (the tuned 1280 and
 // 2560 convolutions of that batch, 2 and 1 lines per block, ran 6 % and 1 %
-// slower with them in registers).
+// slower with them in registers; FP64 as well: the batch 962 -> 914 ms/step).
 constexpr int rows_per_block(int M, bool fp64);
 constexpr int conv_default_cols(int M, bool fp64);
 template <typename T>
@@ -197,14 +197,14 @@ constexpr int tw_resident_vgprs(int M, int E, bool row) {
   // potential (row pass; 5 VGPRs in FP32, 8 in FP64), or per value the
   // spectrum (column pass)
   const int pre = row ? (E / 2) * ((TBS_PF_ACC ? (sizeof(T) == 4 ? 3 : 4) : 0) + (TBS_PF_V ? (int)(sizeof(T) / 2) : 0))
-                      : (TBS_PF_G ? E * (int)(sizeof(T) / 2) : 0);
+                      : ((TBS_PF_G || (sizeof(T) == 8 && E <= 8)) ? E * (int)(sizeof(T) / 2) : 0);
   return (int)(sizeof(T) / 2) * (E + tw_cache_size(M, E)) + rest * (int)(sizeof(T) / 4) + pre;
 }
 template <typename T>
 constexpr bool tw_resident(int M, int E, bool split, bool row) {
   constexpr bool F64 = sizeof(T) == 8;
   if (!F64 && !row && M % 3 == 0) return TBS_TW_RESIDENT && M >= TBS_TW_MIN_M;
-  if (!F64 && !row && M % 5 == 0) return false;
+  if (!row && M % 5 == 0) return false;
   const int lines = row ? rows_per_block(M, F64) : conv_default_cols(M, F64);
   const int budget = 512 / lds_only_waves<T>(M, E, lines, split);
   const int block_waves_simd = (lines * (M / E) + 255) / 256;  // a block's waves share 4 SIMDs
@@ -472,13 +472,17 @@ __device__ __forceinline__ void col_pass_body(const ColArgs& a, const int lb) {
   if constexpr (TWR) tw_load<T, M, E>(twc, tw, tt);
   // the spectrum values of this line, loaded with the line (TBS_PREFETCH) so
   // that their latency overlaps the forward FFT
-  constexpr int EG = (CONV && TBS_PF_G) ? E : 1;
+  // (always for FP64 lines of 8 values per thread or fewer: with the 3D z
+  // convolution at 512 the FP64 harmonic3d step ran 86.7 -> 81.5 ms; the
+  // FP32 one lost a wave per SIMD to the registers and ran 0.4 % slower)
+  constexpr bool PFG = TBS_PF_G || (sizeof(T) == 8 && E <= 8);
+  constexpr int EG = (CONV && PFG) ? E : 1;
   cx<T> pre_g[EG];
   int64_t gb = 0;
   if constexpr (CONV) {
     const int kx = blk * a.cb + c0 + (col % a.cb);
     gb = fold(kx, a.mx) * a.g_sx + fold(i0, a.mm) * a.g_sm;
-    if constexpr (TBS_PF_G) {
+    if constexpr (PFG) {
 #pragma unroll
       for (int j = 0; j < E; ++j) pre_g[j] = gld<T>(a.ghat, gb + fold(tt + j * TPT, M));
     }
@@ -490,7 +494,7 @@ __device__ __forceinline__ void col_pass_body(const ColArgs& a, const int lb) {
   if constexpr (CONV) {
 #pragma unroll
     for (int j = 0; j < E; ++j) {
-      const cx<T> gv = TBS_PF_G ? pre_g[j % EG] : gld<T>(a.ghat, gb + fold(tt + j * TPT, M));
+      const cx<T> gv = PFG ? pre_g[j % EG] : gld<T>(a.ghat, gb + fold(tt + j * TPT, M));
       v[j] = a.conj_g ? cmulc(v[j], gv) : cmul(v[j], gv);
     }
   }
