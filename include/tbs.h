@@ -350,16 +350,18 @@ typedef struct tbs_batch tbs_batch;
  * share the dtype and be tabulated; the batch queues its work on the first
  * plan's stream.  The plans must outlive the batch.  Schedule: each plan's
  * right-hand sides are cut into tiles of at most TBS_BATCH_TILE_RHS (default
- * 4), and consecutive tiles (in plan order) are packed into sets whose working
+ * 2), and consecutive tiles (in plan order) are packed into sets whose working
  * set (intermediate, sum, compensation, potential and spectrum of one term)
  * stays within TBS_BATCH_CACHE_MB megabytes (default 256, sized for the
  * 256 MB last-level cache; 0 runs all plans as one set of whole plans).  The
  * sets run one after the other, each its whole series, so that a set's data
- * stays cache-resident between passes.  Within a set, passes of tiles whose
- * padded lengths coincide run in one grouped kernel launch per term.  With
- * the environment variable TBS_BATCH_CHAINS=2 (and two or more plans) the
- * whole plans are split in two halves of equal size whose pass sequences run
- * on two streams, one pass apart (one set).  TBS_BATCH_SHAPE="nr,nc" sets
+ * stays cache-resident between passes.  The tiles of a set alternate between
+ * two launch chains on two streams (forked at the start of the set, joined at
+ * its end; with one set of whole plans, the plans split in two halves of equal
+ * work), so that one chain's launches fill the compute units the other's
+ * leave idle at their ends; TBS_BATCH_CHAINS=1 runs one chain.  Within a set
+ * and chain, passes of tiles whose padded lengths coincide run in one grouped
+ * kernel launch per term.  TBS_BATCH_SHAPE="nr,nc" sets
  * the rows and columns per block of the member plans whose shapes no tuner has
  * chosen, where their lengths have those shapes.  Results are bitwise the
  * same for every schedule and block shape. */

@@ -22,7 +22,10 @@
 using tbs::zd;
 
 #ifndef TBS_BATCH_CHAINS_DEFAULT
-#define TBS_BATCH_CHAINS_DEFAULT 1
+#define TBS_BATCH_CHAINS_DEFAULT 2
+#endif
+#ifndef TBS_BATCH_TILE_RHS_DEFAULT
+#define TBS_BATCH_TILE_RHS_DEFAULT 2
 #endif
 
 struct tbs_plan {
@@ -650,10 +653,11 @@ struct tbs_batch {
   hipStream_t stream = nullptr;   // the batch's own stream (graphs are recorded and run here)
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   bool fp64 = false;
-  // Two chains: two pass sequences on two streams, the second one pass behind
-  // the first, so that one chain's launches fill the CUs the other's leave
-  // idle: with one set of whole plans, the plans split in two halves of equal
-  // work; with sets of tiles, the even and the odd sets.
+  // Two chains: two pass sequences on two streams, so that one chain's
+  // launches fill the CUs the other's leave idle at their ends: the tiles of
+  // each set alternate between the chains (with one set of whole plans, the
+  // plans split in two halves of equal work), and the sets still run one
+  // after the other (fork and join per set), so the cache holds one set.
   int chains = 1;
   hipStream_t stream2 = nullptr;
   hipEvent_t ev_lag = nullptr, ev_join = nullptr;
@@ -736,14 +740,14 @@ double tile_bytes(const tbs_plan* p, int nrhs) {
 }
 
 // Split the plans into tiles of at most TBS_BATCH_TILE_RHS right-hand sides
-// (default 4) and pack consecutive tiles into sets of at most
+// (default 2) and pack consecutive tiles into sets of at most
 // TBS_BATCH_CACHE_MB megabytes of working set (default 256; 0: one set of
-// whole plans).  With two launch chains, even sets run on the first and odd
-// sets on the second.
+// whole plans).  With two launch chains, the tiles of a set alternate
+// between them.
 void batch_tile(tbs_batch* b) {
   const int nplans = (int)b->plans.size();
   double cap = 256e6;
-  int trhs = 4;
+  int trhs = TBS_BATCH_TILE_RHS_DEFAULT;
   if (const char* e = std::getenv("TBS_BATCH_CACHE_MB")) cap = std::atof(e) * 1e6;
   if (const char* e = std::getenv("TBS_BATCH_TILE_RHS")) trhs = std::max(1, std::atoi(e));
   b->tiles.clear();
@@ -758,6 +762,7 @@ void batch_tile(tbs_batch* b) {
   int set = 0;
   double acc = 0.0;
   bool empty = true;
+  int in_set = 0;  // tiles already in the current set
   for (int i = 0; i < nplans; ++i) {
     const tbs_plan* p = b->plans[i];
     for (int r0 = 0; r0 < p->batch; r0 += trhs) {
@@ -766,8 +771,10 @@ void batch_tile(tbs_batch* b) {
       if (!empty && acc + w > cap) {
         ++set;
         acc = 0.0;
+        in_set = 0;
       }
-      b->tiles.push_back({i, r0, nr, set, b->chains == 2 ? set % 2 : 0});
+      b->tiles.push_back({i, r0, nr, set, b->chains == 2 ? in_set % 2 : 0});
+      ++in_set;
       acc += w;
       empty = false;
     }
@@ -918,9 +925,9 @@ hipEvent_t batch_prof_begin(tbs_batch* b, int e, hipStream_t s) {
   return b->ev_pool[idx + 1];
 }
 
-// Enqueue the whole batched series (no synchronisation).  With two chains the
-// second runs on stream2, forked from the batch stream after the first
-// chain's first row pass and joined back at the end.
+// Enqueue the whole batched series (no synchronisation).  With two chains
+// each set's second chain runs on stream2, forked from the batch stream at
+// the start of the set and joined back at its end.
 int batch_enqueue(tbs_batch* b, int L) {
   const int nt = (int)b->tiles.size();
   const tbs::RowArgs* drow = (const tbs::RowArgs*)b->d_row;
@@ -951,36 +958,32 @@ int batch_enqueue(tbs_batch* b, int L) {
     }
     return TBS_OK;
   };
-  auto series = [&](int chain, hipStream_t s, hipEvent_t after_first) -> int {
-    for (int set = 0; set < b->nsets; ++set) {
-      for (int n = 0; n <= L; ++n) {
-        int rc = rows(chain, set, n, s);
-        if (rc) return rc;
-        if (set == 0 && n == 0 && after_first && hipEventRecord(after_first, s) != hipSuccess)
-          return bfail(b, TBS_ERR_HIP, "batch chain event");
-        if (n == L) break;
-        rc = cols(chain, set, s);
-        if (rc) return rc;
-      }
+  // one set's series on one chain: the row passes of term n, then (n < L)
+  // the column convolutions
+  auto set_series = [&](int chain, int set, hipStream_t s) -> int {
+    for (int n = 0; n <= L; ++n) {
+      int rc = rows(chain, set, n, s);
+      if (rc) return rc;
+      if (n == L) break;
+      rc = cols(chain, set, s);
+      if (rc) return rc;
     }
     return TBS_OK;
   };
   // profiled solves run the chains one after the other on one stream, so
   // that every launch's events bracket that launch alone
   const bool two = b->chains == 2 && !b->prof;
-  int rc = series(0, b->stream, two ? b->ev_lag : nullptr);
-  if (!rc && two) {
-    if (hipStreamWaitEvent(b->stream2, b->ev_lag, 0) != hipSuccess)
+  for (int set = 0; set < b->nsets; ++set) {
+    if (two && (hipEventRecord(b->ev_lag, b->stream) != hipSuccess ||
+                hipStreamWaitEvent(b->stream2, b->ev_lag, 0) != hipSuccess))
       return bfail(b, TBS_ERR_HIP, "batch chain fork");
-    rc = series(1, b->stream2, nullptr);
-  } else if (!rc && b->chains == 2) {
-    rc = series(1, b->stream, nullptr);
+    int rc = set_series(0, set, b->stream);
+    if (!rc && b->chains == 2) rc = set_series(1, set, two ? b->stream2 : b->stream);
+    if (rc) return rc;
+    if (two && (hipEventRecord(b->ev_join, b->stream2) != hipSuccess ||
+                hipStreamWaitEvent(b->stream, b->ev_join, 0) != hipSuccess))
+      return bfail(b, TBS_ERR_HIP, "batch chain join");
   }
-  if (rc) return rc;
-  // a plan's tiles may sit on both chains: the norms after the join
-  if (two && (hipEventRecord(b->ev_join, b->stream2) != hipSuccess ||
-              hipStreamWaitEvent(b->stream, b->ev_join, 0) != hipSuccess))
-    return bfail(b, TBS_ERR_HIP, "batch chain join");
   for (size_t i = 0; i < b->plans.size(); ++i) {
     tbs_plan* p = b->plans[i];
     int e = tbs::launch_finish_norms(p->partials, L, L, p->batch, row_blocks(p), p->resid, b->stream);
@@ -1979,9 +1982,9 @@ int tbs_batch_create(tbs_batch** out, tbs_plan* const* plans, int nplans) {
     tbs_batch_destroy(b);
     return fail(nullptr, TBS_ERR_HIP, "batch stream/events");
   }
-  // one launch chain, or two for batches of several plans (TBS_BATCH_CHAINS=2)
-  b->chains = nplans >= 2 ? TBS_BATCH_CHAINS_DEFAULT : 1;
-  if (const char* env = std::getenv("TBS_BATCH_CHAINS")) b->chains = (std::atoi(env) == 2 && nplans >= 2) ? 2 : 1;
+  // two launch chains, or one (TBS_BATCH_CHAINS=1)
+  b->chains = TBS_BATCH_CHAINS_DEFAULT;
+  if (const char* env = std::getenv("TBS_BATCH_CHAINS")) b->chains = std::atoi(env) == 2 ? 2 : 1;
   if (b->chains == 2 &&
       (hipStreamCreateWithFlags(&b->stream2, hipStreamNonBlocking) != hipSuccess ||
        hipEventCreateWithFlags(&b->ev_lag, hipEventDisableTiming) != hipSuccess ||
@@ -2206,13 +2209,13 @@ int tbs_batch_autotune(tbs_batch* b, const void* const* sources, const void* con
     for (const auto& q : parts) k += (k.empty() ? "" : ",") + q;
     return k;
   };
-  // the tiles of each set whose plan is one of mem: the launches the solves
-  // make for one pass kind of one length, set by set
+  // the tiles of each set and chain whose plan is one of mem: the launches
+  // the solves make for one pass kind of one length
   auto set_tiles = [&](const std::vector<int>& mem) {
-    std::vector<std::vector<int>> out((size_t)b->nsets);
+    std::vector<std::vector<int>> out((size_t)b->nsets * 2);
     for (int t = 0; t < nt; ++t)
       if (std::find(mem.begin(), mem.end(), b->tiles[t].plan) != mem.end())
-        out[(size_t)b->tiles[t].set].push_back(t);
+        out[(size_t)b->tiles[t].set * 2 + b->tiles[t].chain].push_back(t);
     return out;
   };
   // one candidate: every set's grouped launch of these tiles, timed and summed

@@ -135,15 +135,17 @@ def test_batch_rerecords_after_member_plan_grows(dev):
 
 
 def test_two_launch_chains_are_bitwise_one(dev, monkeypatch):
-    """TBS_BATCH_CHAINS=2 (two streams, one pass apart) against the default
-    single chain: the same kernels on the same data, bitwise."""
+    """The default two launch chains (the tiles of each set alternating
+    between two streams) against one chain (TBS_BATCH_CHAINS=1): the same
+    kernels on the same data, bitwise, replays included."""
     import paper_2507_13754_amd as tbs
     cs = cases(nangles=2, nterms=6)
     plans, srcs, pots = build(dev, cs, "c64")
+    monkeypatch.setenv("TBS_BATCH_CHAINS", "1")
     one = tbs.Batch(plans)
     ref = [o.clone() for o in one.solve(srcs, pots, 6)]
     one.close()
-    monkeypatch.setenv("TBS_BATCH_CHAINS", "2")
+    monkeypatch.delenv("TBS_BATCH_CHAINS")
     two = tbs.Batch(plans)
     outs, res = two.solve(srcs, pots, 6, residual=True)
     for a, b in zip(ref, outs):
@@ -186,8 +188,9 @@ def test_batch_autotune_is_bitwise_neutral_and_cached(dev, tmp_path, monkeypatch
 @pytest.mark.parametrize("dt", ["c64", "c128"])
 def test_tile_schedules_are_bitwise_one_set(dev, monkeypatch, dt):
     """The cache-sized schedule (right-hand sides cut into tiles, tiles packed
-    into sets that run their whole series one after the other) against all
-    plans as one set of whole plans: the same arithmetic per right-hand side,
+    into sets that run their whole series one after the other, the tiles of
+    a set alternating between two streams) against all plans as one set of
+    whole plans on one stream: the same arithmetic per right-hand side,
     bitwise, with the residual histories; uneven tiles (5 RHS in tiles of
     3 + 2 and 4 + 1) and many small sets included, with one grid of the full
     broadband size."""
@@ -195,11 +198,13 @@ def test_tile_schedules_are_bitwise_one_set(dev, monkeypatch, dt):
     cs = cases(nangles=3, nterms=5) + [workloads.broadband(40, nangles=5, nterms=5)]
     plans, srcs, pots = build(dev, cs, dt)
     monkeypatch.setenv("TBS_BATCH_CACHE_MB", "0")
+    monkeypatch.setenv("TBS_BATCH_CHAINS", "1")
     whole = tbs.Batch(plans)
     ref, rref = whole.solve(srcs, pots, 5, residual=True)
     ref = [o.clone() for o in ref]
     whole.close()
-    for cap, trhs in (("200", "4"), ("20", "3"), ("1", "1")):
+    monkeypatch.delenv("TBS_BATCH_CHAINS")
+    for cap, trhs in (("0", "2"), ("200", "4"), ("256", "2"), ("20", "3"), ("1", "1")):
         monkeypatch.setenv("TBS_BATCH_CACHE_MB", cap)
         monkeypatch.setenv("TBS_BATCH_TILE_RHS", trhs)
         tiled = tbs.Batch(plans)
