@@ -267,13 +267,24 @@ def run_broadband(dev, steps: int, warmup: int, fp64: bool, tune: bool, counters
         nbytes_compiled = sum(series_bytes_2d(nx, ny, B, L, fp, mx, my) for nx, ny, B, mx, my in geo)
         r = {"ms": ms, "wall_ms": wall, "value": gpts / (ms * 1e-3), "bytes": nbytes,
              "bytes_compiled": nbytes_compiled, "gpts": gpts, "build_s": t_build}
-        # per-launch event timing of the same solve (no graph replay while profiled)
-        batch.profile(True)
+        # per-launch event timing of the same series (no graph replay while
+        # profiled), on a one-chain batch over the same plans and tuned shapes:
+        # both tiles of a set in one launch, the launches one after the other,
+        # so that each kernel's time is its own (the solve above runs the
+        # set's tiles on two streams side by side)
+        prev = os.environ.get("TBS_BATCH_CHAINS")
+        os.environ["TBS_BATCH_CHAINS"] = "1"
+        pbatch = tbs.Batch(plans)
+        if prev is None:
+            del os.environ["TBS_BATCH_CHAINS"]
+        else:
+            os.environ["TBS_BATCH_CHAINS"] = prev
+        pbatch.profile(True)
         nprof = max(2, min(3, steps))
         for _ in range(nprof):
-            batch.solve(srcs, pots, L, outs=outs)
-        prof = batch.profile_read()
-        batch.profile(False)
+            pbatch.solve(srcs, pots, L, outs=outs)
+        prof = pbatch.profile_read()
+        pbatch.close()
         # one entry per kernel (pass kind, FFT length, lines per block): the
         # batch splits the grids of one length between its two launch chains,
         # i.e. two grouped launches of the same kernel per term
