@@ -660,7 +660,7 @@ struct tbs_batch {
   // after the other (fork and join per set), so the cache holds one set.
   int chains = 1;
   hipStream_t stream2 = nullptr;
-  hipEvent_t ev_lag = nullptr, ev_join = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;  // per set: second chain starts, ends
   // Tiles: a plan's right-hand sides [r0, r0 + nrhs).  Sets: tiles whose
   // working set (intermediate, sum, compensation, potential, spectrum) fits
   // the device's last-level cache together; the series runs set by set (all
@@ -974,8 +974,8 @@ int batch_enqueue(tbs_batch* b, int L) {
   // that every launch's events bracket that launch alone
   const bool two = b->chains == 2 && !b->prof;
   for (int set = 0; set < b->nsets; ++set) {
-    if (two && (hipEventRecord(b->ev_lag, b->stream) != hipSuccess ||
-                hipStreamWaitEvent(b->stream2, b->ev_lag, 0) != hipSuccess))
+    if (two && (hipEventRecord(b->ev_fork, b->stream) != hipSuccess ||
+                hipStreamWaitEvent(b->stream2, b->ev_fork, 0) != hipSuccess))
       return bfail(b, TBS_ERR_HIP, "batch chain fork");
     int rc = set_series(0, set, b->stream);
     if (!rc && b->chains == 2) rc = set_series(1, set, two ? b->stream2 : b->stream);
@@ -1987,7 +1987,7 @@ int tbs_batch_create(tbs_batch** out, tbs_plan* const* plans, int nplans) {
   if (const char* env = std::getenv("TBS_BATCH_CHAINS")) b->chains = std::atoi(env) == 2 ? 2 : 1;
   if (b->chains == 2 &&
       (hipStreamCreateWithFlags(&b->stream2, hipStreamNonBlocking) != hipSuccess ||
-       hipEventCreateWithFlags(&b->ev_lag, hipEventDisableTiming) != hipSuccess ||
+       hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) != hipSuccess ||
        hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming) != hipSuccess)) {
     (void)hipGetLastError();
     tbs_batch_destroy(b);
@@ -2387,7 +2387,7 @@ void tbs_batch_destroy(tbs_batch* b) {
   if (b->ev_in) (void)hipEventDestroy(b->ev_in);
   if (b->ev_out) (void)hipEventDestroy(b->ev_out);
   if (b->stream2) (void)hipStreamSynchronize(b->stream2);
-  if (b->ev_lag) (void)hipEventDestroy(b->ev_lag);
+  if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
   if (b->ev_join) (void)hipEventDestroy(b->ev_join);
   if (b->stream2) (void)hipStreamDestroy(b->stream2);
   if (b->stream) (void)hipStreamDestroy(b->stream);
