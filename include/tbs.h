@@ -363,8 +363,9 @@ typedef struct tbs_batch tbs_batch;
  * and chain, passes of tiles whose padded lengths coincide run in one grouped
  * kernel launch per term.  TBS_BATCH_SHAPE="nr,nc" sets
  * the rows and columns per block of the member plans whose shapes no tuner has
- * chosen, where their lengths have those shapes.  Results are bitwise the
- * same for every schedule and block shape. */
+ * chosen, where their lengths have those shapes.  Fields are bitwise the
+ * same for every schedule and block shape; the residual norms are FP64 sums
+ * of per-block partials, whose order follows the rows per row-pass block. */
 int tbs_batch_create(tbs_batch **out, tbs_plan *const *plans, int nplans);
 
 /* The L-term series of every plan in the batch (the tbs_solve contract per
