@@ -355,13 +355,13 @@ typedef struct tbs_batch tbs_batch;
  * stays within TBS_BATCH_CACHE_MB megabytes (default 256, sized for the
  * 256 MB last-level cache; 0 runs all plans as one set of whole plans).  The
  * sets run one after the other, each its whole series, so that a set's data
- * stays cache-resident between passes.  The tiles of a set alternate between
- * two launch chains on two streams (forked at the start of the set, joined at
- * its end; with one set of whole plans, the plans split in two halves of equal
- * work), so that one chain's launches fill the compute units the other's
- * leave idle at their ends; TBS_BATCH_CHAINS=1 runs one chain.  Within a set
- * and chain, passes of tiles whose padded lengths coincide run in one grouped
- * kernel launch per term.  TBS_BATCH_SHAPE="nr,nc" sets
+ * stays cache-resident between passes.  The tiles of a set go in turn to
+ * TBS_BATCH_CHAINS launch chains (1 .. 4, default 3) on their own streams
+ * (forked at the start of the set, joined at its end; with one set of whole
+ * plans, the plans split into parts of equal work), so that one chain's
+ * launches fill the compute units the others' leave idle at their ends.
+ * Within a set and chain, passes of tiles whose padded lengths coincide run in
+ * one grouped kernel launch per term.  TBS_BATCH_SHAPE="nr,nc" sets
  * the rows and columns per block of the member plans whose shapes no tuner has
  * chosen, where their lengths have those shapes.  Fields are bitwise the
  * same for every schedule and block shape; the residual norms are FP64 sums

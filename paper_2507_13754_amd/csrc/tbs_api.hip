@@ -22,8 +22,9 @@
 using tbs::zd;
 
 #ifndef TBS_BATCH_CHAINS_DEFAULT
-#define TBS_BATCH_CHAINS_DEFAULT 2
+#define TBS_BATCH_CHAINS_DEFAULT 3
 #endif
+constexpr int kMaxChains = 4;
 #ifndef TBS_BATCH_TILE_RHS_DEFAULT
 #define TBS_BATCH_TILE_RHS_DEFAULT 2
 #endif
@@ -653,14 +654,15 @@ struct tbs_batch {
   hipStream_t stream = nullptr;   // the batch's own stream (graphs are recorded and run here)
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   bool fp64 = false;
-  // Two chains: two pass sequences on two streams, so that one chain's
-  // launches fill the CUs the other's leave idle at their ends: the tiles of
-  // each set alternate between the chains (with one set of whole plans, the
-  // plans split in two halves of equal work), and the sets still run one
-  // after the other (fork and join per set), so the cache holds one set.
+  // Launch chains: pass sequences on their own streams, so that one chain's
+  // launches fill the CUs the others' leave idle at their ends: the tiles of
+  // each set go to the chains in turn (with one set of whole plans, the plans
+  // split into parts of equal work), and the sets still run one after the
+  // other (fork and join per set), so the cache holds one set.
   int chains = 1;
-  hipStream_t stream2 = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;  // per set: second chain starts, ends
+  hipStream_t cstream[kMaxChains] = {};  // chain c > 0 runs on cstream[c]
+  hipEvent_t ev_fork = nullptr;          // per set: the other chains start
+  hipEvent_t ev_join[kMaxChains] = {};   // per set: chain c has ended
   // Tiles: a plan's right-hand sides [r0, r0 + nrhs).  Sets: tiles whose
   // working set (intermediate, sum, compensation, potential, spectrum) fits
   // the device's last-level cache together; the series runs set by set (all
@@ -742,8 +744,7 @@ double tile_bytes(const tbs_plan* p, int nrhs) {
 // Split the plans into tiles of at most TBS_BATCH_TILE_RHS right-hand sides
 // (default 2) and pack consecutive tiles into sets of at most
 // TBS_BATCH_CACHE_MB megabytes of working set (default 256; 0: one set of
-// whole plans).  With two launch chains, the tiles of a set alternate
-// between them.
+// whole plans).  The tiles of a set go to the launch chains in turn.
 void batch_tile(tbs_batch* b) {
   const int nplans = (int)b->plans.size();
   double cap = 256e6;
@@ -773,7 +774,7 @@ void batch_tile(tbs_batch* b) {
         acc = 0.0;
         in_set = 0;
       }
-      b->tiles.push_back({i, r0, nr, set, b->chains == 2 ? in_set % 2 : 0});
+      b->tiles.push_back({i, r0, nr, set, in_set % b->chains});
       ++in_set;
       acc += w;
       empty = false;
@@ -925,9 +926,17 @@ hipEvent_t batch_prof_begin(tbs_batch* b, int e, hipStream_t s) {
   return b->ev_pool[idx + 1];
 }
 
-// Enqueue the whole batched series (no synchronisation).  With two chains
-// each set's second chain runs on stream2, forked from the batch stream at
-// the start of the set and joined back at its end.
+// Waits for the batch stream and the chains' streams; false on a failed solve.
+bool batch_sync(tbs_batch* b) {
+  bool ok = !b->stream || hipStreamSynchronize(b->stream) == hipSuccess;
+  for (int c = 1; c < kMaxChains; ++c)
+    if (b->cstream[c] && hipStreamSynchronize(b->cstream[c]) != hipSuccess) ok = false;
+  return ok;
+}
+
+// Enqueue the whole batched series (no synchronisation).  With several
+// chains each set's chains c > 0 run on their own streams, forked from the
+// batch stream at the start of the set and joined back at its end.
 int batch_enqueue(tbs_batch* b, int L) {
   const int nt = (int)b->tiles.size();
   const tbs::RowArgs* drow = (const tbs::RowArgs*)b->d_row;
@@ -972,17 +981,21 @@ int batch_enqueue(tbs_batch* b, int L) {
   };
   // profiled solves run the chains one after the other on one stream, so
   // that every launch's events bracket that launch alone
-  const bool two = b->chains == 2 && !b->prof;
+  const bool many = b->chains > 1 && !b->prof;
   for (int set = 0; set < b->nsets; ++set) {
-    if (two && (hipEventRecord(b->ev_fork, b->stream) != hipSuccess ||
-                hipStreamWaitEvent(b->stream2, b->ev_fork, 0) != hipSuccess))
+    if (many && hipEventRecord(b->ev_fork, b->stream) != hipSuccess)
       return bfail(b, TBS_ERR_HIP, "batch chain fork");
-    int rc = set_series(0, set, b->stream);
-    if (!rc && b->chains == 2) rc = set_series(1, set, two ? b->stream2 : b->stream);
-    if (rc) return rc;
-    if (two && (hipEventRecord(b->ev_join, b->stream2) != hipSuccess ||
-                hipStreamWaitEvent(b->stream, b->ev_join, 0) != hipSuccess))
-      return bfail(b, TBS_ERR_HIP, "batch chain join");
+    for (int c = 1; many && c < b->chains; ++c)
+      if (hipStreamWaitEvent(b->cstream[c], b->ev_fork, 0) != hipSuccess)
+        return bfail(b, TBS_ERR_HIP, "batch chain fork");
+    for (int c = 0; c < b->chains; ++c) {
+      const int rc = set_series(c, set, many && c > 0 ? b->cstream[c] : b->stream);
+      if (rc) return rc;
+    }
+    for (int c = 1; many && c < b->chains; ++c)
+      if (hipEventRecord(b->ev_join[c], b->cstream[c]) != hipSuccess ||
+          hipStreamWaitEvent(b->stream, b->ev_join[c], 0) != hipSuccess)
+        return bfail(b, TBS_ERR_HIP, "batch chain join");
   }
   for (size_t i = 0; i < b->plans.size(); ++i) {
     tbs_plan* p = b->plans[i];
@@ -1982,27 +1995,30 @@ int tbs_batch_create(tbs_batch** out, tbs_plan* const* plans, int nplans) {
     tbs_batch_destroy(b);
     return fail(nullptr, TBS_ERR_HIP, "batch stream/events");
   }
-  // two launch chains, or one (TBS_BATCH_CHAINS=1)
+  // launch chains: TBS_BATCH_CHAINS (1 .. 4), default 3
   b->chains = TBS_BATCH_CHAINS_DEFAULT;
-  if (const char* env = std::getenv("TBS_BATCH_CHAINS")) b->chains = std::atoi(env) == 2 ? 2 : 1;
-  if (b->chains == 2 &&
-      (hipStreamCreateWithFlags(&b->stream2, hipStreamNonBlocking) != hipSuccess ||
-       hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) != hipSuccess ||
-       hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming) != hipSuccess)) {
+  if (const char* env = std::getenv("TBS_BATCH_CHAINS")) b->chains = std::atoi(env);
+  b->chains = std::max(1, std::min(kMaxChains, b->chains));
+  bool ok = b->chains == 1 || hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) == hipSuccess;
+  for (int c = 1; ok && c < b->chains; ++c)
+    ok = hipStreamCreateWithFlags(&b->cstream[c], hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreateWithFlags(&b->ev_join[c], hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
     (void)hipGetLastError();
     tbs_batch_destroy(b);
-    return fail(nullptr, TBS_ERR_HIP, "batch second stream/events");
+    return fail(nullptr, TBS_ERR_HIP, "batch chain streams/events");
   }
-  // balance the chains by work (points x right-hand sides), largest first
+  // one set of whole plans: the chains balanced by work (points x
+  // right-hand sides), largest plan first to the lightest chain
   b->chain_of.assign(nplans, 0);
-  if (b->chains == 2) {
+  {
     std::vector<int> order(nplans);
     for (int i = 0; i < nplans; ++i) order[i] = i;
     auto work = [&](int i) { return (double)b->plans[i]->M[0] * b->plans[i]->M[1] * b->plans[i]->batch; };
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work(x) > work(y); });
-    double w[2] = {0.0, 0.0};
+    double w[kMaxChains] = {0.0, 0.0, 0.0, 0.0};
     for (int i : order) {
-      const int c = w[1] < w[0] ? 1 : 0;
+      const int c = (int)(std::min_element(w, w + b->chains) - w);
       b->chain_of[i] = c;
       w[c] += work(i);
     }
@@ -2045,9 +2061,7 @@ int tbs_batch_solve(tbs_batch* b, const void* const* sources, const void* const*
   const bool ready = b->tables_ready && key == b->key && L == b->key_L;
   if (!ready) {
     // a previous solve may still read the descriptor tables
-    if (hipStreamSynchronize(b->stream) != hipSuccess ||
-        (b->stream2 && hipStreamSynchronize(b->stream2) != hipSuccess))
-      return bfail(b, TBS_ERR_HIP, "batch: previous solve failed");
+    if (!batch_sync(b)) return bfail(b, TBS_ERR_HIP, "batch: previous solve failed");
     batch_drop_graph(b);
     // per-plan scratch for L terms, then the descriptor tables
     for (tbs_plan* p : b->plans) {
@@ -2153,9 +2167,7 @@ int tbs_batch_autotune(tbs_batch* b, const void* const* sources, const void* con
   for (int i = 0; i < np; ++i)
     if (!sources[i] || !potentials[i] || !p_outs[i])
       return bfail(b, TBS_ERR_INVALID, "batch tuning needs source, potential and output per plan");
-  if (hipStreamSynchronize(b->stream) != hipSuccess ||
-      (b->stream2 && hipStreamSynchronize(b->stream2) != hipSuccess))
-    return bfail(b, TBS_ERR_HIP, "batch: previous solve failed");
+  if (!batch_sync(b)) return bfail(b, TBS_ERR_HIP, "batch: previous solve failed");
   batch_drop_graph(b);
   const hipStream_t s = b->plans[0]->stream;
   for (tbs_plan* p : b->plans) {
@@ -2212,10 +2224,10 @@ int tbs_batch_autotune(tbs_batch* b, const void* const* sources, const void* con
   // the tiles of each set and chain whose plan is one of mem: the launches
   // the solves make for one pass kind of one length
   auto set_tiles = [&](const std::vector<int>& mem) {
-    std::vector<std::vector<int>> out((size_t)b->nsets * 2);
+    std::vector<std::vector<int>> out((size_t)b->nsets * kMaxChains);
     for (int t = 0; t < nt; ++t)
       if (std::find(mem.begin(), mem.end(), b->tiles[t].plan) != mem.end())
-        out[(size_t)b->tiles[t].set * 2 + b->tiles[t].chain].push_back(t);
+        out[(size_t)b->tiles[t].set * kMaxChains + b->tiles[t].chain].push_back(t);
     return out;
   };
   // one candidate: every set's grouped launch of these tiles, timed and summed
@@ -2386,10 +2398,12 @@ void tbs_batch_destroy(tbs_batch* b) {
   batch_free_tables(b);
   if (b->ev_in) (void)hipEventDestroy(b->ev_in);
   if (b->ev_out) (void)hipEventDestroy(b->ev_out);
-  if (b->stream2) (void)hipStreamSynchronize(b->stream2);
+  (void)batch_sync(b);
   if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
-  if (b->ev_join) (void)hipEventDestroy(b->ev_join);
-  if (b->stream2) (void)hipStreamDestroy(b->stream2);
+  for (int c = 1; c < kMaxChains; ++c) {
+    if (b->ev_join[c]) (void)hipEventDestroy(b->ev_join[c]);
+    if (b->cstream[c]) (void)hipStreamDestroy(b->cstream[c]);
+  }
   if (b->stream) (void)hipStreamDestroy(b->stream);
   if (b->counted)
     for (tbs_plan* p : b->plans) p->batch_refs -= 1;

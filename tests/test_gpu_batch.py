@@ -134,26 +134,33 @@ def test_batch_rerecords_after_member_plan_grows(dev):
         p.close()
 
 
-def test_two_launch_chains_are_bitwise_one(dev, monkeypatch):
-    """The default two launch chains (the tiles of each set alternating
-    between two streams) against one chain (TBS_BATCH_CHAINS=1): the same
-    kernels on the same data, bitwise, replays included."""
+def test_launch_chains_are_bitwise_one(dev, monkeypatch):
+    """Several launch chains (the tiles of each set going to 2, 3 (the
+    default) or 4 streams in turn) against one chain (TBS_BATCH_CHAINS=1):
+    the same kernels on the same data, bitwise, replays included."""
     import paper_2507_13754_amd as tbs
-    cs = cases(nangles=2, nterms=6)
+    cs = cases(nangles=2, nterms=6) + [workloads.broadband(40, nangles=4, nterms=6)]
     plans, srcs, pots = build(dev, cs, "c64")
     monkeypatch.setenv("TBS_BATCH_CHAINS", "1")
     one = tbs.Batch(plans)
-    ref = [o.clone() for o in one.solve(srcs, pots, 6)]
+    ref, rref = one.solve(srcs, pots, 6, residual=True)
+    ref = [o.clone() for o in ref]
     one.close()
-    monkeypatch.delenv("TBS_BATCH_CHAINS")
-    two = tbs.Batch(plans)
-    outs, res = two.solve(srcs, pots, 6, residual=True)
-    for a, b in zip(ref, outs):
-        assert torch.equal(a, b)
-    outs2 = two.solve(srcs, pots, 6, outs=outs)
-    for a, b in zip(ref, outs2):
-        assert torch.equal(a, b)
-    two.close()
+    for k in ("2", None, "4"):
+        if k is None:
+            monkeypatch.delenv("TBS_BATCH_CHAINS")
+        else:
+            monkeypatch.setenv("TBS_BATCH_CHAINS", k)
+        many = tbs.Batch(plans)
+        outs, res = many.solve(srcs, pots, 6, residual=True)
+        for a, b in zip(ref, outs):
+            assert torch.equal(a, b), k
+        for a, b in zip(rref, res):
+            assert np.array_equal(a, b), k
+        outs2 = many.solve(srcs, pots, 6, outs=outs)
+        for a, b in zip(ref, outs2):
+            assert torch.equal(a, b), k
+        many.close()
     for p in plans:
         p.close()
 
