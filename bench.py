@@ -269,9 +269,9 @@ def run_broadband(dev, steps: int, warmup: int, fp64: bool, tune: bool, counters
              "bytes_compiled": nbytes_compiled, "gpts": gpts, "build_s": t_build}
         # per-launch event timing of the same series (no graph replay while
         # profiled), on a one-chain batch over the same plans and tuned shapes:
-        # both tiles of a set in one launch, the launches one after the other,
+        # all tiles of a set in one launch, the launches one after the other,
         # so that each kernel's time is its own (the solve above runs the
-        # set's tiles on two streams side by side)
+        # set's tiles on several streams side by side)
         prev = os.environ.get("TBS_BATCH_CHAINS")
         os.environ["TBS_BATCH_CHAINS"] = "1"
         pbatch = tbs.Batch(plans)
@@ -909,8 +909,9 @@ def main():
         "config": {"workload": "broadband: 48 frequencies 2-8 MHz (f_i = 2 + 6 i/47 MHz), each on its own "
                                "lambda/6 grid over 4 x 4 cm (312^2 .. 1247^2), 16-blob absorbing-dispersive "
                                "medium, 64-element array with 16 steering angles (-30..30 deg) per frequency, "
-                               "25 terms, one batch (right-hand sides in tiles of 4, cache-sized sets run one "
-                               "after another) replayed as one recorded HIP graph",
+                               "25 terms, one batch (right-hand sides in tiles of 2, cache-sized sets run one "
+                               "after another, the tiles of a set on three streams) replayed as one recorded "
+                               "HIP graph",
                    "grids": len(bb["geo"]), "rhs_per_grid": B, "nterms": L,
                    "physical_points": int(sum(g[0] * g[1] for g in bb["geo"])),
                    "padded_lengths": lengths,

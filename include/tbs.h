@@ -352,8 +352,10 @@ typedef struct tbs_batch tbs_batch;
  * right-hand sides are cut into tiles of at most TBS_BATCH_TILE_RHS (default
  * 2), and consecutive tiles (in plan order) are packed into sets whose working
  * set (intermediate, sum, compensation, potential and spectrum of one term)
- * stays within TBS_BATCH_CACHE_MB megabytes (default 256, sized for the
- * 256 MB last-level cache; 0 runs all plans as one set of whole plans).  The
+ * stays within TBS_BATCH_CACHE_MB megabytes (default 280, sized for the
+ * 256 MB last-level cache: the estimate counts the potential and spectrum of
+ * a plan once per tile although its tiles in a set share them; 0 runs all
+ * plans as one set of whole plans).  The
  * sets run one after the other, each its whole series, so that a set's data
  * stays cache-resident between passes.  The tiles of a set go in turn to
  * TBS_BATCH_CHAINS launch chains (1 .. 4, default 3) on their own streams

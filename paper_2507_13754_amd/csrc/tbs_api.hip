@@ -743,11 +743,13 @@ double tile_bytes(const tbs_plan* p, int nrhs) {
 
 // Split the plans into tiles of at most TBS_BATCH_TILE_RHS right-hand sides
 // (default 2) and pack consecutive tiles into sets of at most
-// TBS_BATCH_CACHE_MB megabytes of working set (default 256; 0: one set of
-// whole plans).  The tiles of a set go to the launch chains in turn.
+// TBS_BATCH_CACHE_MB megabytes of working set (default 280; 0: one set of
+// whole plans).  The estimate counts each tile's potential and spectrum, which
+// tiles of one plan in a set share: 280 MB of it holds three tiles of the
+// smaller 2560-line grids, about 225 MB of distinct data for the 256 MB cache.  The tiles of a set go to the launch chains in turn.
 void batch_tile(tbs_batch* b) {
   const int nplans = (int)b->plans.size();
-  double cap = 256e6;
+  double cap = 280e6;
   int trhs = TBS_BATCH_TILE_RHS_DEFAULT;
   if (const char* e = std::getenv("TBS_BATCH_CACHE_MB")) cap = std::atof(e) * 1e6;
   if (const char* e = std::getenv("TBS_BATCH_TILE_RHS")) trhs = std::max(1, std::atoi(e));
