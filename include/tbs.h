@@ -383,7 +383,9 @@ int tbs_batch_solve(tbs_batch *batch, const void *const *sources, const void *co
  * plans of one y length) by timing each bitwise-neutral candidate as the
  * grouped launches the solves make for it (one per set of tiles, a middle
  * term) on the given buffers (same meaning as in tbs_batch_solve; the
- * contents of p_outs are undefined afterwards), and regroup.  Choices are
+ * contents of p_outs are undefined afterwards); then, with the cache-sized
+ * schedule and unless TBS_BATCH_CHAINS is set, the number of launch chains
+ * (1 .. 4) by timing a 4-term series replay per count; and regroup.  Choices are
  * kept per device model, dtype, length, member shapes and tiling for the life
  * of the process, and in the file named by the environment variable
  * TBS_TUNE_CACHE when it is set (read on first use, appended to;

@@ -2001,8 +2001,9 @@ int tbs_batch_create(tbs_batch** out, tbs_plan* const* plans, int nplans) {
   b->chains = TBS_BATCH_CHAINS_DEFAULT;
   if (const char* env = std::getenv("TBS_BATCH_CHAINS")) b->chains = std::atoi(env);
   b->chains = std::max(1, std::min(kMaxChains, b->chains));
-  bool ok = b->chains == 1 || hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) == hipSuccess;
-  for (int c = 1; ok && c < b->chains; ++c)
+  // streams for every chain count tbs_batch_autotune may choose
+  bool ok = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) == hipSuccess;
+  for (int c = 1; ok && c < kMaxChains; ++c)
     ok = hipStreamCreateWithFlags(&b->cstream[c], hipStreamNonBlocking) == hipSuccess &&
          hipEventCreateWithFlags(&b->ev_join[c], hipEventDisableTiming) == hipSuccess;
   if (!ok) {
@@ -2331,9 +2332,62 @@ int tbs_batch_autotune(tbs_batch* b, const void* const* sources, const void* con
   if (e1) (void)hipEventDestroy(e1);
   if (d_desc) (void)hipFree(d_desc);
   if (d_st) (void)hipFree(d_st);
+  // launch chains of the cache-sized schedule (unless TBS_BATCH_CHAINS fixes
+  // them): a short series (4 terms) per chain count, the second of two solves
+  // (a graph replay) timed; one choice for the whole batch
+  if (!rc && b->tile_rhs > 0 && !std::getenv("TBS_BATCH_CHAINS")) {
+    std::vector<int> all(np);
+    for (int i = 0; i < np; ++i) all[i] = i;
+    const std::string key = "batchchains " + tag + " " + members_key(all) + sched;
+    std::vector<int> v;
+    int pick = b->chains;
+    if (tune_lookup(key, &v) && v.size() == 1 && v[0] >= 1 && v[0] <= kMaxChains) {
+      pick = v[0];
+    } else {
+      const hipStream_t cs = b->plans[0]->stream;
+      hipEvent_t t0 = nullptr, t1 = nullptr;
+      if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess) {
+        (void)hipGetLastError();
+        rc = bfail(b, TBS_ERR_HIP, "batch tuning events");
+      }
+      double best = 1e30;
+      for (int K = 1; K <= kMaxChains && !rc; ++K) {
+        b->chains = K;
+        const int g = batch_group(b);
+        if (g) {
+          rc = bfail(b, g, "batch tables");
+          break;
+        }
+        batch_drop_graph(b);
+        float ms = 0.f;
+        int e = tbs_batch_solve(b, sources, potentials, 4, p_outs, nullptr);
+        if (e >= 0) {
+          if (hipEventRecord(t0, cs) != hipSuccess) e = TBS_ERR_HIP;
+          if (e >= 0) e = tbs_batch_solve(b, sources, potentials, 4, p_outs, nullptr);
+          if (e >= 0 && (hipEventRecord(t1, cs) != hipSuccess || hipEventSynchronize(t1) != hipSuccess ||
+                         hipEventElapsedTime(&ms, t0, t1) != hipSuccess))
+            e = TBS_ERR_HIP;
+        }
+        if (e < 0) {
+          rc = bfail(b, e, "batch chain tuning solve");
+          break;
+        }
+        if (ms < best) {
+          best = ms;
+          pick = K;
+        }
+      }
+      if (t0) (void)hipEventDestroy(t0);
+      if (t1) (void)hipEventDestroy(t1);
+      if (!rc) tune_store(key, {pick});
+    }
+    b->chains = pick;
+  }
   // regroup with the chosen shapes (also after a failure: shapes may have moved)
   const int grc = batch_group(b);
   if (!rc && grc) rc = bfail(b, grc, "batch tables");
+  if (!batch_sync(b) && !rc) rc = bfail(b, TBS_ERR_HIP, "batch tuning");
+  batch_drop_graph(b);
   return rc;
 }
 

@@ -167,8 +167,9 @@ def test_launch_chains_are_bitwise_one(dev, monkeypatch):
 
 @pytest.mark.parametrize("dt", ["c64", "c128"])
 def test_batch_autotune_is_bitwise_neutral_and_cached(dev, tmp_path, monkeypatch, dt):
-    """tbs_batch_autotune times the grouped launches' block shapes and
-    regroups: the fields after tuning equal the untuned ones bitwise (every
+    """tbs_batch_autotune times the grouped launches' block shapes and the
+    number of launch chains and regroups: the fields after tuning equal the
+    untuned ones bitwise (every
     block shape of a length keeps its twiddle factors where the default shape
     does, 2560 lines with 1, 2 or 4 columns and 2 or 4 rows per block
     included), and the choices land in the TBS_TUNE_CACHE file."""
@@ -187,7 +188,8 @@ def test_batch_autotune_is_bitwise_neutral_and_cached(dev, tmp_path, monkeypatch
     batch.close()
     lines = cache.read_text().splitlines() if cache.exists() else []
     # only lengths with more than one candidate shape are timed and stored
-    assert all(" = " in ln and ln.split()[0] in ("batchrow", "batchcol") for ln in lines)
+    assert all(" = " in ln and ln.split()[0] in ("batchrow", "batchcol", "batchchains") for ln in lines)
+    assert any(ln.startswith("batchchains ") for ln in lines)
     for p in plans:
         p.close()
 
